@@ -1,0 +1,137 @@
+"""ctypes binding of librs.so: the C ABI of include/rs.h, names unchanged.
+
+Argument marshalling only -- every step of the sort runs in the library's
+HIP kernels.  Device pointers may be given as ints or as torch tensors
+(their ``data_ptr()``); ``stream`` may be an int handle, a
+``torch.cuda.Stream``, or None for torch's current stream.  A missing
+library raises ``RSError``; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librs.so")
+
+RS_OK = 0
+RS_KEY_U32, RS_KEY_U64, RS_KEY_FIXED_I64, RS_KEY_STR = 0, 1, 2, 3
+RS_FLAG_VALIDATE = 1
+RS_MAX_ELEMENTS = (1 << 30) - 1
+
+KINDS = {"u32": RS_KEY_U32, "u64": RS_KEY_U64, "fixed_i64": RS_KEY_FIXED_I64, "str": RS_KEY_STR}
+
+EXPORTED = ["rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_batched_temp_bytes", "rs_sort_batched",
+            "rs_status_string", "rs_last_error"]
+
+
+class RSError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+class KeyDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("base", ctypes.c_uint32), ("ndims", ctypes.c_uint32),
+                ("frac_digits", ctypes.c_uint32), ("str_width", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+def key_desc(kind: str | int, base: int = 0, ndims: int = 0, frac_digits: int = 0, str_width: int = 0,
+             validate: bool = False) -> KeyDesc:
+    k = KINDS[kind] if isinstance(kind, str) else int(kind)
+    if k == RS_KEY_STR and not str_width:
+        str_width = 16
+    return KeyDesc(k, base, ndims, frac_digits, str_width, RS_FLAG_VALIDATE if validate else 0)
+
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Loads librs.so (once).  Raises RSError when it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RSError(-1, f"{p} is missing: build it with `python -m paper_2107_01391_amd.build_lib` "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(p)
+    vp, u64, u32, sz = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_size_t
+    dp = ctypes.POINTER(KeyDesc)
+    lib.rs_temp_bytes.argtypes = [dp, u64, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.rs_sort_keys.argtypes = [dp, vp, vp, u64, vp, sz, vp]
+    lib.rs_sort_pairs.argtypes = [dp, vp, vp, vp, vp, u64, vp, sz, vp]
+    lib.rs_batched_temp_bytes.argtypes = [dp, u64, u32, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.rs_sort_batched.argtypes = [dp, vp, vp, vp, vp, vp, u32, u64, vp, sz, vp]
+    for f in ("rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_batched_temp_bytes", "rs_sort_batched"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.rs_status_string.argtypes = [ctypes.c_int]
+    lib.rs_status_string.restype = ctypes.c_char_p
+    lib.rs_last_error.argtypes = []
+    lib.rs_last_error.restype = ctypes.c_char_p
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _check(st: int):
+    if st != RS_OK:
+        lib = load_library()
+        raise RSError(st, f"{lib.rs_status_string(st).decode()}: {lib.rs_last_error().decode()}")
+
+
+def rs_status_string(status: int) -> str:
+    return load_library().rs_status_string(status).decode()
+
+
+def rs_last_error() -> str:
+    return load_library().rs_last_error().decode()
+
+
+def rs_temp_bytes(desc: KeyDesc, n: int, with_values: bool) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().rs_temp_bytes(ctypes.byref(desc), n, int(bool(with_values)), ctypes.byref(out)))
+    return out.value
+
+
+def rs_sort_keys(desc: KeyDesc, keys_in, keys_out, n: int, tmp, tmp_bytes: int, stream=None) -> None:
+    _check(load_library().rs_sort_keys(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), n, _ptr(tmp), tmp_bytes,
+                                       _stream(stream)))
+
+
+def rs_sort_pairs(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, n: int, tmp, tmp_bytes: int,
+                  stream=None) -> None:
+    _check(load_library().rs_sort_pairs(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                        _ptr(vals_out), n, _ptr(tmp), tmp_bytes, _stream(stream)))
+
+
+def rs_batched_temp_bytes(desc: KeyDesc, total: int, nseg: int, with_values: bool) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().rs_batched_temp_bytes(ctypes.byref(desc), total, nseg, int(bool(with_values)),
+                                                ctypes.byref(out)))
+    return out.value
+
+
+def rs_sort_batched(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, nseg: int, total: int, tmp,
+                    tmp_bytes: int, stream=None) -> None:
+    _check(load_library().rs_sort_batched(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                          _ptr(vals_out), _ptr(d_seg_offsets), nseg, total, _ptr(tmp), tmp_bytes,
+                                          _stream(stream)))

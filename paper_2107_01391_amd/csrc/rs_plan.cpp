@@ -1,0 +1,254 @@
+// rs_plan.cpp -- host planner (no device code).
+#include "rs_plan.h"
+
+#include <string.h>
+
+namespace rs {
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static bool mul_fits(uint64_t a, uint64_t b, uint64_t limit, uint64_t *out) {
+  if (a != 0 && b > limit / a) return false;
+  *out = a * b;
+  return true;
+}
+
+rs_status key_info(const rs_key_desc *desc, KeyInfo *ki, std::string *why) {
+  if (!desc) {
+    *why = "desc is NULL";
+    return RS_ERR_NULL_ARG;
+  }
+  memset(ki, 0, sizeof *ki);
+  ki->kind = desc->kind;
+  switch (desc->kind) {
+  case RS_KEY_U32:
+    ki->key_bytes = 4;
+    ki->base = desc->base ? desc->base : 256;
+    break;
+  case RS_KEY_U64:
+    ki->key_bytes = 8;
+    ki->base = desc->base ? desc->base : 256;
+    break;
+  case RS_KEY_FIXED_I64:
+    ki->key_bytes = 8;
+    ki->base = desc->base ? desc->base : 10;
+    break;
+  case RS_KEY_STR:
+    if (desc->str_width != 16) {
+      *why = "strings: only str_width == 16 is supported";
+      return RS_ERR_UNSUPPORTED;
+    }
+    if (desc->base && desc->base != 27) {
+      *why = "strings: base must be 27 (pad + a..z)";
+      return RS_ERR_BAD_DESC;
+    }
+    ki->key_bytes = 16;
+    ki->base = 27;
+    ki->str_width = 16;
+    if (desc->ndims && desc->ndims != 16) {
+      *why = "strings: ndims must equal str_width";
+      return RS_ERR_BAD_DESC;
+    }
+    ki->ndims = 16;
+    break;
+  default:
+    *why = "unknown key kind";
+    return RS_ERR_BAD_DESC;
+  }
+  if (ki->base < 2 || ki->base > 65536) {
+    *why = "base must be in [2, 65536]";
+    return RS_ERR_BAD_DESC;
+  }
+  ki->pow2 = (ki->base & (ki->base - 1)) == 0;
+  ki->log2_base = 0;
+  while ((1u << ki->log2_base) < ki->base) ++ki->log2_base;
+  if (desc->kind != RS_KEY_STR) {
+    const uint32_t value_bits = ki->key_bytes * 8;
+    if (desc->ndims) {
+      ki->ndims = desc->ndims;
+    } else {  // enough digits for every value of the type (non-negative for fixed point)
+      const uint32_t need_bits = desc->kind == RS_KEY_FIXED_I64 ? 63 : value_bits;
+      unsigned __int128 cap = 1, lim = (unsigned __int128)1 << need_bits;
+      uint32_t d = 0;
+      while (cap < lim) {
+        cap *= ki->base;
+        ++d;
+      }
+      ki->ndims = d;
+    }
+    if (ki->ndims == 0 || ki->ndims > 64) {
+      *why = "ndims must be in [1, 64]";
+      return RS_ERR_BAD_DESC;
+    }
+    // a space wider than the key type is allowed only if its top digit is
+    // still reachable (no dimension that every key has as zero beyond it)
+    unsigned __int128 below_top = 1;
+    for (uint32_t i = 0; i + 1 < ki->ndims; ++i) {
+      below_top *= ki->base;
+      if (below_top > ((unsigned __int128)1 << 64)) break;
+    }
+    if (below_top >= ((unsigned __int128)1 << value_bits)) {
+      *why = "ndims larger than the key type can fill";
+      return RS_ERR_BAD_DESC;
+    }
+  }
+  uint64_t sp = 1;
+  ki->space = 0;
+  bool fits64 = true;
+  for (uint32_t i = 0; i < ki->ndims; ++i)
+    if (!mul_fits(sp, ki->base, UINT64_MAX, &sp)) {
+      fits64 = false;
+      break;
+    }
+  if (fits64) ki->space = sp;
+  ki->space_fits32 = fits64 && sp <= (1ull << 32);
+  return RS_OK;
+}
+
+rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tuning &tune, Plan *plan,
+                    std::string *why) {
+  Plan &p = *plan;
+  p = Plan();
+  rs_status st = key_info(desc, &p.key, why);
+  if (st != RS_OK) return st;
+  if (n > RS_MAX_ELEMENTS) {
+    *why = "n exceeds RS_MAX_ELEMENTS (counts are 30-bit in the look-back words)";
+    return RS_ERR_UNSUPPORTED;
+  }
+  const KeyInfo &k = p.key;
+  p.pairs = pairs;
+  p.n = n;
+
+  // keys alone on a small integer space: the literal count / scan / emit
+  if (!pairs && k.kind != RS_KEY_STR && k.space && k.space <= kLiteralMaxCells &&
+      k.space <= (n * 4 > 65536 ? n * 4 : 65536)) {
+    p.literal = true;
+    p.literal_cells = (uint32_t)k.space;
+  }
+
+  // dimension groups, least significant first
+  uint32_t dims_per_pass;
+  if (k.kind == RS_KEY_STR) {
+    p.mode = kModeStr16;
+    dims_per_pass = 1;
+    while (dims_per_pass < 3) {
+      uint64_t c = 1;
+      for (uint32_t i = 0; i <= dims_per_pass; ++i) c *= 27;
+      if (c > tune.max_cells) break;
+      ++dims_per_pass;
+    }
+  } else if (k.pow2) {
+    p.mode = kModePow2;
+    if (k.log2_base > 11) {
+      *why = "power-of-two base above 2^11 is not supported";
+      return RS_ERR_UNSUPPORTED;
+    }
+    dims_per_pass = tune.digit_bits / k.log2_base;
+    if (dims_per_pass == 0) dims_per_pass = 1;
+  } else {
+    p.mode = (k.kind == RS_KEY_U32 || k.space_fits32) ? kModeDiv32 : kModeDiv64;
+    if (k.base > tune.max_cells) {
+      *why = "base above the per-pass cell limit";
+      return RS_ERR_UNSUPPORTED;
+    }
+    dims_per_pass = 1;
+    for (;;) {
+      uint64_t c = 1;
+      for (uint32_t i = 0; i <= dims_per_pass; ++i) c *= k.base;
+      if (c > tune.max_cells || dims_per_pass + 1 > k.ndims) break;
+      ++dims_per_pass;
+    }
+  }
+  p.npasses = (k.ndims + dims_per_pass - 1) / dims_per_pass;
+  if (p.npasses > (uint32_t)kMaxPasses) {
+    *why = "too many passes for this description";
+    return RS_ERR_UNSUPPORTED;
+  }
+  p.bins = 0;
+  for (uint32_t i = 0; i < p.npasses; ++i) {
+    const uint32_t lo = i * dims_per_pass;
+    const uint32_t w = (k.ndims - lo) < dims_per_pass ? (k.ndims - lo) : dims_per_pass;
+    uint64_t cells = 1, below = 1;
+    for (uint32_t j = 0; j < w; ++j) cells *= k.base;
+    for (uint32_t j = 0; j < lo && below <= UINT64_MAX / k.base; ++j) below *= k.base;
+    p.pass_cells[i] = (uint32_t)cells;
+    if (cells > p.bins) p.bins = (uint32_t)cells;
+    switch (p.mode) {
+    case kModePow2:
+      p.p2[i].shift = lo * k.log2_base;
+      p.p2[i].mask = (uint32_t)(cells - 1);
+      break;
+    case kModeDiv32:
+      p.d32[i].by_lo = make_fastdiv32((uint32_t)below);
+      p.d32[i].by_cells = make_fastdiv32((uint32_t)cells);
+      p.d32[i].cells = (uint32_t)cells;
+      break;
+    case kModeDiv64:
+      p.d64[i].by_lo = make_fastdiv64(below);
+      p.d64[i].by_cells = make_fastdiv64(cells);
+      p.d64[i].cells = (uint32_t)cells;
+      break;
+    case kModeStr16:
+      p.s16[i].pos = k.ndims - lo - w;
+      p.s16[i].width = w;
+      break;
+    }
+  }
+  p.bits = p.bins <= 256 ? 8 : (p.bins <= 1024 ? 10 : 11);
+  if (p.bins > 2048) {
+    *why = "a pass with more than 2048 cells is not supported";
+    return RS_ERR_UNSUPPORTED;
+  }
+
+  if ((size_t)p.npasses * p.bins * 4 > 64 * 1024) {
+    *why = "the passes' count tables exceed 64 KiB of LDS";
+    return RS_ERR_UNSUPPORTED;
+  }
+
+  // tile shape: 256 threads; keys per thread sized so that the LDS staging
+  // of one tile stays at 32 KiB for wide keys
+  p.block = 256;
+  p.kpt = k.key_bytes >= 16 ? 8 : 16;
+  p.tile = p.block * p.kpt;
+  p.ntiles = (n + p.tile - 1) / p.tile;
+
+  // histogram grid: enough workgroups to fill 256 CUs, partial tables capped
+  const uint64_t words = (uint64_t)p.npasses * p.bins;
+  uint64_t g = (n + 16383) / 16384;
+  uint64_t cap = (2u << 20) / (words ? words : 1);
+  if (cap < 1) cap = 1;
+  if (g > 1024) g = 1024;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  p.hist_grid = (uint32_t)g;
+
+  // scratch layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  if (p.literal) {
+    // counts and control words are contiguous so one fill clears both
+    p.scan_chunks = (p.literal_cells + kScanChunk - 1) / kScanChunk;
+    p.off_counts = take((size_t)p.literal_cells * 4);
+    p.off_ctrl = take(((size_t)p.scan_chunks + 1) * 4);
+    p.ctrl_bytes = off - p.off_counts;
+    p.off_starts = take((size_t)p.literal_cells * 4);
+  } else {
+    p.off_keys_alt = take((size_t)n * k.key_bytes);
+    if (pairs) p.off_vals_alt = take((size_t)n * 4);
+    p.off_partials = take((size_t)p.hist_grid * words * 4);
+    p.off_dstart = take(words * 4);
+    p.status_bytes = align_up((size_t)p.npasses * p.ntiles * p.bins * 4, 256);
+    p.off_status = take(p.status_bytes);
+    p.scan_chunks = p.npasses * ((p.bins + kScanChunk - 1) / kScanChunk);
+    p.ctrl_bytes = align_up(((size_t)p.npasses + 1 + p.scan_chunks) * 4, 256);
+    p.off_ctrl = take(p.ctrl_bytes);
+  }
+  p.total = off ? off : 256;
+  return RS_OK;
+}
+
+}  // namespace rs

@@ -1,0 +1,72 @@
+// rs_plan.h -- host planner of the gfx950 Recombinant Sort path.
+//
+// Turns a key description into the passes of the hot path: how the N digit
+// dimensions are grouped (one count space per group, least significant group
+// sorted first so that the stable passes compose to the lexicographic order
+// of the whole space), which codec extracts a group's cell, the tile shape
+// of the kernels, and the layout of the caller's scratch buffer.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/rs.h"
+#include "rs_device.h"
+
+namespace rs {
+
+enum DigitMode { kModePow2 = 0, kModeDiv32 = 1, kModeDiv64 = 2, kModeStr16 = 3 };
+
+struct KeyInfo {
+  uint32_t kind, base, ndims, key_bytes, str_width;
+  bool pow2;
+  uint32_t log2_base;
+  bool space_fits32;    // b^N <= 2^32
+  uint64_t space;       // b^N when it fits 64 bits, else 0
+};
+
+struct Tuning {
+  uint32_t digit_bits = 8;   // target width of a pass (power-of-two bases)
+  uint32_t max_cells = 1024; // largest count space of one pass (other bases)
+};
+
+struct Plan {
+  KeyInfo key;
+  bool pairs = false;
+  bool literal = false;      // keys only, whole space counted at once
+  uint32_t literal_cells = 0;
+
+  DigitMode mode = kModePow2;
+  uint32_t npasses = 0;
+  uint32_t bins = 0;         // cells of the widest pass
+  uint32_t bits = 8;         // kernel variant: 8, 10 or 11 bits of cell index
+  uint32_t pass_cells[kMaxPasses] = {};
+  DigitPow2 p2[kMaxPasses] = {};
+  DigitDiv32 d32[kMaxPasses] = {};
+  DigitDiv64 d64[kMaxPasses] = {};
+  DigitStr16 s16[kMaxPasses] = {};
+
+  uint32_t block = 256, kpt = 16, tile = 4096;
+  uint64_t n = 0, ntiles = 0;
+  uint32_t hist_grid = 1;
+
+  // scratch layout (byte offsets into tmp)
+  size_t off_keys_alt = 0, off_vals_alt = 0, off_partials = 0, off_dstart = 0, off_status = 0;
+  size_t off_ctrl = 0, ctrl_bytes = 0, status_bytes = 0;
+  size_t off_counts = 0, off_starts = 0;
+  size_t total = 0;
+  uint32_t scan_chunks = 0;  // chunks of the cell scan
+};
+
+rs_status key_info(const rs_key_desc *desc, KeyInfo *ki, std::string *why);
+rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tuning &tune, Plan *plan,
+                    std::string *why);
+
+constexpr uint32_t kScanBlock = 256;
+constexpr uint32_t kScanItems = 8;
+constexpr uint32_t kScanChunk = kScanBlock * kScanItems;
+constexpr uint32_t kLiteralMaxCells = 1u << 24;
+
+}  // namespace rs

@@ -1,0 +1,354 @@
+// rs_sort.hip -- C ABI and launch sequences of the single-array sort.
+//
+// rs_sort_pairs / rs_sort_keys (grouped passes):
+//   1. rs_fill                 clear the control words
+//   2. rs_digit_hash_histogram one read of the keys: every pass's cell counts
+//                              (per-workgroup tables), clears look-back words
+//   3. rs_cell_scan            exclusive scan of every pass's counts
+//   4. rs_rank_scatter x P     stable passes, least significant group first,
+//                              ping-ponging between the output and scratch
+// rs_sort_keys on a small space (literal):
+//   1. rs_fill                 clear the cell counts
+//   2. rs_cell_count           S[cell]++ over the whole space
+//   3. rs_cell_scan            running output position per cell
+//   4. rs_cell_emit            count copies of each cell's rebuilt key
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "rs_internal.h"
+#include "rs_kernels.h"
+
+namespace rs {
+
+thread_local std::string g_last_error;
+
+rs_status fail(rs_status st, const std::string &why) {
+  g_last_error = why;
+  return st;
+}
+
+int cu_count() {
+  static int cached = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      cached = cus;
+    if (cached <= 0) cached = 256;
+  });
+  return cached;
+}
+
+rs_status check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(RS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return RS_OK;
+}
+
+rs_status launch_fill(void *p, size_t bytes, uint32_t value, hipStream_t stream) {
+  if (bytes == 0) return RS_OK;
+  const uint64_t n16 = bytes / 16;
+  uint64_t blocks = (n16 + 255) / 256;
+  const uint64_t cap = (uint64_t)cu_count() * 8;
+  if (blocks > cap) blocks = cap;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(rs_fill, dim3((uint32_t)blocks), dim3(256), 0, stream, (uint4 *)p, n16, value);
+  return check_launch("rs_fill");
+}
+
+// --------------------------------------------------------- grouped passes
+
+template <typename K, class Digit, int BITS>
+static rs_status run_passes(const Plan &pl, const Digit *digits, const void *keys_in, void *keys_out,
+                            const uint32_t *vals_in, uint32_t *vals_out, void *tmp, hipStream_t stream) {
+  char *base = (char *)tmp;
+  uint32_t *ctrl = (uint32_t *)(base + pl.off_ctrl);
+  uint32_t *partials = (uint32_t *)(base + pl.off_partials);
+  uint32_t *dstart = (uint32_t *)(base + pl.off_dstart);
+  uint32_t *status = (uint32_t *)(base + pl.off_status);
+  rs_status st = launch_fill(ctrl, pl.ctrl_bytes, 0, stream);
+  if (st != RS_OK) return st;
+
+  // 2. histogram of every pass in one read
+  HistParams<Digit> h;
+  memset(&h, 0, sizeof h);
+  for (uint32_t i = 0; i < pl.npasses; ++i) h.digit[i] = digits[i];
+  h.npasses = pl.npasses;
+  h.stride = pl.bins;
+  h.n = pl.n;
+  h.partials = partials;
+  h.zero = (uint4 *)status;
+  h.zero16 = pl.status_bytes / 16;
+  const size_t lds = (size_t)pl.npasses * pl.bins * 4;
+  if (((uintptr_t)keys_in % 16) == 0) {
+    hipLaunchKernelGGL((rs_digit_hash_histogram<K, Digit, 256>), dim3(pl.hist_grid), dim3(256), lds, stream, h,
+                       (const K *)keys_in);
+  } else {
+    return fail(RS_ERR_UNSUPPORTED, "keys_in must be 16-byte aligned");
+  }
+  if ((st = check_launch("rs_digit_hash_histogram")) != RS_OK) return st;
+
+  // 3. exclusive scan of each pass's cells
+  ScanParams s;
+  s.in = partials;
+  s.part_stride = (uint64_t)pl.npasses * pl.bins;
+  s.nparts = pl.hist_grid;
+  s.nseg = pl.npasses;
+  s.cells = pl.bins;
+  s.stride = pl.bins;
+  s.out = dstart;
+  s.chunk_counter = ctrl + pl.npasses;
+  s.chunk_status = ctrl + pl.npasses + 1;
+  s.chunks_per_seg = (pl.bins + kScanChunk - 1) / kScanChunk;
+  s.nseg_dev = nullptr;
+  s.nseg_mul = 1;
+  hipLaunchKernelGGL((rs_cell_scan<kScanBlock, kScanItems>), dim3(s.nseg * s.chunks_per_seg), dim3(kScanBlock), 0,
+                     stream, s);
+  if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
+
+  // 4. stable passes; buffer X = output, Y = scratch; pass P-1 writes X
+  const size_t kb = pl.key.key_bytes;
+  K *X = (K *)keys_out;
+  K *Y = (K *)(base + pl.off_keys_alt);
+  uint32_t *XV = vals_out;
+  uint32_t *YV = (uint32_t *)(base + pl.off_vals_alt);
+  const K *src = (const K *)keys_in;
+  const uint32_t *srcv = vals_in;
+  const bool odd = pl.npasses % 2 == 1;
+  if (odd && keys_in == keys_out) {
+    // pass 0 would read and write X: start from a copy in Y
+    if (hipMemcpyAsync(Y, keys_in, pl.n * kb, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return fail(RS_ERR_HIP, "hipMemcpyAsync");
+    src = Y;
+  }
+  if (pl.pairs && odd && vals_in == vals_out) {
+    if (hipMemcpyAsync(YV, vals_in, pl.n * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return fail(RS_ERR_HIP, "hipMemcpyAsync");
+    srcv = YV;
+  }
+  for (uint32_t i = 0; i < pl.npasses; ++i) {
+    const bool to_x = ((pl.npasses - 1 - i) % 2) == 0;
+    K *dst = to_x ? X : Y;
+    uint32_t *dstv = to_x ? XV : YV;
+    PassParams<Digit> pp;
+    memset(&pp, 0, sizeof pp);
+    pp.digit = digits[i];
+    pp.bins = pl.pass_cells[i];
+    pp.n = pl.n;
+    pp.digit_start = dstart + (size_t)i * pl.bins;
+    pp.status = status + (size_t)i * pl.ntiles * pl.bins;
+    pp.tile_counter = ctrl + i;
+    const dim3 grid((uint32_t)pl.ntiles), blk(256);
+    constexpr int KPT = sizeof(K) >= 16 ? 8 : 16;  // LDS staging of one tile: 32 KiB at most
+    if (pl.pairs)
+      hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, true, false>), grid, blk, 0, stream, pp, src, dst,
+                         srcv, dstv);
+    else
+      hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, false, false>), grid, blk, 0, stream, pp, src,
+                         dst, nullptr, nullptr);
+    if ((st = check_launch("rs_rank_scatter")) != RS_OK) return st;
+    src = dst;
+    srcv = dstv;
+  }
+  return RS_OK;
+}
+
+template <typename K, class Digit>
+static rs_status run_bits(const Plan &pl, const Digit *digits, const void *ki, void *ko, const uint32_t *vi,
+                          uint32_t *vo, void *tmp, hipStream_t s) {
+  switch (pl.bits) {
+  case 8:
+    return run_passes<K, Digit, 8>(pl, digits, ki, ko, vi, vo, tmp, s);
+  case 10:
+    return run_passes<K, Digit, 10>(pl, digits, ki, ko, vi, vo, tmp, s);
+  default:
+    return run_passes<K, Digit, 11>(pl, digits, ki, ko, vi, vo, tmp, s);
+  }
+}
+
+static rs_status run_literal(const Plan &pl, const void *keys_in, void *keys_out, void *tmp, hipStream_t stream) {
+  char *base = (char *)tmp;
+  uint32_t *counts = (uint32_t *)(base + pl.off_counts);
+  uint32_t *starts = (uint32_t *)(base + pl.off_starts);
+  uint32_t *ctrl = (uint32_t *)(base + pl.off_ctrl);
+  rs_status st = launch_fill(counts, pl.ctrl_bytes, 0, stream);
+  if (st != RS_OK) return st;
+  uint64_t blocks = (pl.n + 255) / 256;
+  const uint64_t cap = (uint64_t)cu_count() * 16;
+  if (blocks > cap) blocks = cap;
+  if (pl.key.key_bytes == 4)
+    hipLaunchKernelGGL((rs_cell_count<uint32_t, 256>), dim3((uint32_t)blocks), dim3(256), 0, stream,
+                       (const uint32_t *)keys_in, pl.n, pl.literal_cells, counts);
+  else
+    hipLaunchKernelGGL((rs_cell_count<uint64_t, 256>), dim3((uint32_t)blocks), dim3(256), 0, stream,
+                       (const uint64_t *)keys_in, pl.n, pl.literal_cells, counts);
+  if ((st = check_launch("rs_cell_count")) != RS_OK) return st;
+  ScanParams s;
+  s.in = counts;
+  s.part_stride = 0;
+  s.nparts = 1;
+  s.nseg = 1;
+  s.cells = pl.literal_cells;
+  s.stride = pl.literal_cells;
+  s.out = starts;
+  s.chunk_counter = ctrl;
+  s.chunk_status = ctrl + 1;
+  s.chunks_per_seg = pl.scan_chunks;
+  s.nseg_dev = nullptr;
+  s.nseg_mul = 1;
+  hipLaunchKernelGGL((rs_cell_scan<kScanBlock, kScanItems>), dim3(pl.scan_chunks), dim3(kScanBlock), 0, stream, s);
+  if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
+  const uint32_t eb = (pl.literal_cells + 255) / 256;
+  if (pl.key.key_bytes == 4)
+    hipLaunchKernelGGL((rs_cell_emit<uint32_t, 256>), dim3(eb), dim3(256), 0, stream, counts, starts,
+                       pl.literal_cells, (uint32_t *)keys_out, pl.n);
+  else
+    hipLaunchKernelGGL((rs_cell_emit<uint64_t, 256>), dim3(eb), dim3(256), 0, stream, counts, starts,
+                       pl.literal_cells, (uint64_t *)keys_out, pl.n);
+  return check_launch("rs_cell_emit");
+}
+
+// ------------------------------------------------------------- validation
+
+template <typename K>
+__global__ __launch_bounds__(256) void rs_validate(const K *__restrict__ keys, uint64_t n, uint64_t space,
+                                                   uint32_t *__restrict__ bad) {
+  uint32_t mine = 0;
+  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (uint64_t)gridDim.x * 256) {
+    if constexpr (sizeof(K) == 16) {
+      const Str16 k = keys[e];
+      for (int w = 0; w < 4; ++w)
+        for (int b = 0; b < 4; ++b) {
+          const uint32_t byte = (k.w[w] >> (8 * b)) & 0xffu;
+          mine += (byte != 0 && (byte < 'a' || byte > 'z')) ? 1u : 0u;
+        }
+    } else {
+      mine += ((uint64_t)keys[e] >= space) ? 1u : 0u;
+    }
+  }
+  mine = wave_sum(mine);
+  if (lane_id() == 0 && mine) atomicAdd(bad, mine);
+}
+
+rs_status validate_keys(const Plan &pl, const void *keys, uint64_t n, void *tmp, hipStream_t s) {
+  uint32_t *bad = (uint32_t *)tmp;
+  if (hipMemsetAsync(bad, 0, 4, s) != hipSuccess) return fail(RS_ERR_HIP, "hipMemsetAsync");
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > (uint64_t)cu_count() * 8) blocks = (uint64_t)cu_count() * 8;
+  // fixed point is signed: a negative key reads as a huge unsigned value
+  const uint64_t space = pl.key.space ? pl.key.space : UINT64_MAX;
+  switch (pl.key.key_bytes) {
+  case 4:
+    hipLaunchKernelGGL((rs_validate<uint32_t>), dim3((uint32_t)blocks), dim3(256), 0, s, (const uint32_t *)keys, n,
+                       space, bad);
+    break;
+  case 8:
+    hipLaunchKernelGGL((rs_validate<uint64_t>), dim3((uint32_t)blocks), dim3(256), 0, s, (const uint64_t *)keys, n,
+                       pl.key.kind == RS_KEY_FIXED_I64 && space > (1ull << 63) ? (1ull << 63) : space, bad);
+    break;
+  default:
+    hipLaunchKernelGGL((rs_validate<Str16>), dim3((uint32_t)blocks), dim3(256), 0, s, (const Str16 *)keys, n, 0,
+                       bad);
+  }
+  rs_status st = check_launch("rs_validate");
+  if (st != RS_OK) return st;
+  uint32_t h = 0;
+  if (hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return fail(RS_ERR_HIP, "validation copy");
+  if (h) return fail(RS_ERR_KEY_RANGE, std::to_string(h) + " keys outside the count space");
+  return RS_OK;
+}
+
+rs_status run_plan(const Plan &pl, const void *ki, void *ko, const uint32_t *vi, uint32_t *vo, void *tmp,
+                   hipStream_t s) {
+  if (pl.n == 0) return RS_OK;
+  if (pl.literal) return run_literal(pl, ki, ko, tmp, s);
+  const uint32_t kb = pl.key.key_bytes;
+  switch (pl.mode) {
+  case kModePow2:
+    if (kb == 4) return run_bits<uint32_t, DigitPow2>(pl, pl.p2, ki, ko, vi, vo, tmp, s);
+    return run_bits<uint64_t, DigitPow2>(pl, pl.p2, ki, ko, vi, vo, tmp, s);
+  case kModeDiv32:
+    if (kb == 4) return run_bits<uint32_t, DigitDiv32>(pl, pl.d32, ki, ko, vi, vo, tmp, s);
+    return run_bits<uint64_t, DigitDiv32>(pl, pl.d32, ki, ko, vi, vo, tmp, s);
+  case kModeDiv64:
+    return run_bits<uint64_t, DigitDiv64>(pl, pl.d64, ki, ko, vi, vo, tmp, s);
+  case kModeStr16:
+    return run_bits<Str16, DigitStr16>(pl, pl.s16, ki, ko, vi, vo, tmp, s);
+  }
+  return fail(RS_ERR_BAD_DESC, "unknown digit mode");
+}
+
+}  // namespace rs
+
+using namespace rs;
+
+extern "C" {
+
+const char *rs_status_string(rs_status s) {
+  switch (s) {
+  case RS_OK: return "ok";
+  case RS_ERR_NULL_ARG: return "null argument";
+  case RS_ERR_BAD_DESC: return "bad key description";
+  case RS_ERR_KEY_RANGE: return "key outside the count space";
+  case RS_ERR_TMP_TOO_SMALL: return "scratch buffer too small";
+  case RS_ERR_UNSUPPORTED: return "unsupported size or shape";
+  case RS_ERR_OOM: return "out of host memory";
+  case RS_ERR_HIP: return "HIP runtime error";
+  case RS_ERR_BUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char *rs_last_error(void) { return g_last_error.c_str(); }
+
+rs_status rs_temp_bytes(const rs_key_desc *desc, uint64_t n, int with_values, size_t *bytes) {
+  g_last_error.clear();
+  if (!bytes) return fail(RS_ERR_NULL_ARG, "bytes is NULL");
+  Plan pl;
+  std::string why;
+  rs_status st = make_plan(desc, n, with_values != 0, current_tuning(desc, n, with_values != 0), &pl, &why);
+  if (st != RS_OK) return fail(st, why);
+  *bytes = pl.total;
+  return RS_OK;
+}
+
+static rs_status sort_common(const rs_key_desc *desc, const void *keys_in, void *keys_out, const uint32_t *vals_in,
+                             uint32_t *vals_out, uint64_t n, void *tmp, size_t tmp_bytes, void *stream,
+                             bool pairs) {
+  g_last_error.clear();
+  if (!desc) return fail(RS_ERR_NULL_ARG, "desc is NULL");
+  if (n == 0) return RS_OK;
+  if (!keys_in || !keys_out || !tmp) return fail(RS_ERR_NULL_ARG, "keys_in, keys_out and tmp are required");
+  if (pairs && (!vals_in || !vals_out)) return fail(RS_ERR_NULL_ARG, "vals_in and vals_out are required");
+  Plan pl;
+  std::string why;
+  rs_status st = make_plan(desc, n, pairs, current_tuning(desc, n, pairs), &pl, &why);
+  if (st != RS_OK) return fail(st, why);
+  if (tmp_bytes < pl.total)
+    return fail(RS_ERR_TMP_TOO_SMALL, "tmp_bytes " + std::to_string(tmp_bytes) + " < " + std::to_string(pl.total));
+  if ((uintptr_t)tmp % 256 != 0) return fail(RS_ERR_UNSUPPORTED, "tmp must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  if (desc->flags & RS_FLAG_VALIDATE) {
+    st = validate_keys(pl, keys_in, n, tmp, s);
+    if (st != RS_OK) return st;
+  }
+  return run_plan(pl, keys_in, keys_out, vals_in, vals_out, tmp, s);
+}
+
+rs_status rs_sort_keys(const rs_key_desc *desc, const void *keys_in, void *keys_out, uint64_t n, void *tmp,
+                       size_t tmp_bytes, void *stream) {
+  return sort_common(desc, keys_in, keys_out, nullptr, nullptr, n, tmp, tmp_bytes, stream, false);
+}
+
+rs_status rs_sort_pairs(const rs_key_desc *desc, const void *keys_in, void *keys_out, const uint32_t *vals_in,
+                        uint32_t *vals_out, uint64_t n, void *tmp, size_t tmp_bytes, void *stream) {
+  return sort_common(desc, keys_in, keys_out, vals_in, vals_out, n, tmp, tmp_bytes, stream, true);
+}
+
+}  // extern "C"

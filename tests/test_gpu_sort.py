@@ -1,0 +1,162 @@
+"""Parity of the HIP path with the CPU oracle, element by element, on seeded
+inputs that span several tiles and a ragged tail, plus the edge cases."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2107_01391_amd import _binding as B
+from paper_2107_01391_amd import workloads
+from tests.gpu_helpers import assert_same, gpu_sort, oracle_sort
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _library():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    B.load_library()  # raises when librs.so was not built: no fallback
+
+
+TILE_U32 = 4096  # keys per tile of the 32/64-bit kernels
+TILE_STR = 2048
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, TILE_U32 - 1, TILE_U32, TILE_U32 + 1, 3 * TILE_U32 + 17, 100_003,
+                               1 << 20])
+def test_u32_pairs_base256(n):
+    _say(f"u32 pairs base 256 n={n}")
+    w = workloads.uniform_u32_pairs(n)
+    gk, gv = gpu_sort(w.keys, w.vals, "u32", 256, 4)
+    ok, ov = oracle_sort(w.keys, w.vals, "u32", 256, 4)
+    assert_same(gk, gv, ok, ov, f"n={n}")
+
+
+def test_empty_is_noop():
+    import torch
+    d = B.key_desc("u32")
+    B.rs_sort_pairs(d, 0, 0, 0, 0, 0, 0, 0)
+    B.rs_sort_keys(d, 0, 0, 0, 0, 0)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [1, 1000, 65_537, 1_000_000])
+def test_decimal_keys_literal(n):
+    """Keys only on a 10^6-cell space: count, scan, emit rebuilt keys."""
+    _say(f"decimal keys literal n={n}")
+    w = workloads.uniform_decimal_u32(n)
+    gk, _ = gpu_sort(w.keys, None, "u32", 10, 6)
+    ok, _ = oracle_sort(w.keys, None, "u32", 10, 6, groups=[6])
+    assert_same(gk, None, ok, None, f"n={n}")
+
+
+@pytest.mark.parametrize("n", [5000, 300_001])
+def test_decimal_pairs_base10(n):
+    _say(f"decimal pairs base 10 n={n}")
+    w = workloads.uniform_decimal_u32(n)
+    vals = np.arange(n, dtype=np.uint32)
+    gk, gv = gpu_sort(w.keys, vals, "u32", 10, 6)
+    ok, ov = oracle_sort(w.keys, vals, "u32", 10, 6)
+    assert_same(gk, gv, ok, ov)
+
+
+@pytest.mark.parametrize("n", [4097, 200_003])
+def test_fixed_point_pairs(n):
+    _say(f"fixed point pairs n={n}")
+    w = workloads.fixed_point_decimals(n)
+    gk, gv = gpu_sort(w.keys, w.vals, "fixed_i64", 10, 9, frac_digits=3)
+    ok, ov = oracle_sort(w.keys, w.vals, "fixed_i64", 10, 9)
+    assert_same(gk, gv, ok, ov)
+
+
+@pytest.mark.parametrize("n", [1, 2047, 2049, 50_003])
+def test_strings_pairs(n):
+    _say(f"strings pairs n={n}")
+    w = workloads.strings16(n)
+    gk, gv = gpu_sort(w.keys, w.vals, "str", 27, 16)
+    ok, ov = oracle_sort(w.keys, w.vals, "str", 27, 16)
+    assert_same(gk, gv, ok, ov)
+
+
+def test_strings_keys_only():
+    _say("strings keys only")
+    w = workloads.strings16(30_001)
+    gk, _ = gpu_sort(w.keys, None, "str", 27, 16)
+    ok, _ = oracle_sort(w.keys, None, "str", 27, 16)
+    assert_same(gk, None, ok, None)
+
+
+def test_u64_pairs():
+    _say("u64 pairs")
+    rng = np.random.default_rng(11)
+    keys = rng.integers(0, 2**64, 100_003, dtype=np.uint64)
+    keys[::5] = keys[7]
+    vals = np.arange(keys.shape[0], dtype=np.uint32)
+    gk, gv = gpu_sort(keys, vals, "u64", 256, 8)
+    ok, ov = oracle_sort(keys, vals, "u64", 256, 8)
+    assert_same(gk, gv, ok, ov)
+
+
+def test_u32_keys_only_passes():
+    _say("u32 keys only, grouped passes")
+    w = workloads.uniform_u32_pairs(77_777)
+    gk, _ = gpu_sort(w.keys, None, "u32", 256, 4)
+    ok, _ = oracle_sort(w.keys, None, "u32", 256, 4)
+    assert_same(gk, None, ok, None)
+
+
+@pytest.mark.parametrize("distinct", [1, 2, 3, 17])
+def test_skewed_hot_cells(distinct):
+    """All keys in a handful of cells: the single-cell hot spot of the count."""
+    _say(f"skewed distinct={distinct}")
+    rng = np.random.default_rng(distinct)
+    pool = rng.integers(0, 2**32, distinct, dtype=np.uint32)
+    keys = pool[rng.integers(0, distinct, 150_001)]
+    vals = np.arange(keys.shape[0], dtype=np.uint32)
+    gk, gv = gpu_sort(keys, vals, "u32", 256, 4)
+    ok, ov = oracle_sort(keys, vals, "u32", 256, 4)
+    assert_same(gk, gv, ok, ov)
+
+
+@pytest.mark.parametrize("kind,base,ndims", [("u32", 256, 4), ("fixed_i64", 10, 9)])
+def test_in_place(kind, base, ndims):
+    """keys_out == keys_in: even (4) and odd (3) pass counts."""
+    _say(f"in place {kind}")
+    if kind == "u32":
+        w = workloads.uniform_u32_pairs(123_457)
+    else:
+        w = workloads.fixed_point_decimals(123_457)
+    gk, gv = gpu_sort(w.keys, w.vals, kind, base, ndims, in_place=True)
+    ok, ov = oracle_sort(w.keys, w.vals, kind, base, ndims)
+    assert_same(gk, gv, ok, ov)
+
+
+def test_deterministic_repeat():
+    _say("determinism")
+    w = workloads.uniform_u32_pairs(500_000)
+    a = gpu_sort(w.keys, w.vals, "u32", 256, 4)
+    b = gpu_sort(w.keys, w.vals, "u32", 256, 4)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_validate_rejects_out_of_space_keys():
+    _say("validate")
+    keys = np.array([5, 999_999, 1_000_000, 3], np.uint32)
+    with pytest.raises(B.RSError) as e:
+        gpu_sort(keys, None, "u32", 10, 6, validate=True)
+    assert e.value.status == 3
+    keys = np.array([[ord("a")] + [0] * 14 + [ord("A")]], np.uint8)
+    with pytest.raises(B.RSError) as e:
+        gpu_sort(keys, np.zeros(1, np.uint32), "str", 27, 16, validate=True)
+    assert e.value.status == 3
+    ok_keys = np.array([5, 999_999, 3], np.uint32)
+    gk, _ = gpu_sort(ok_keys, None, "u32", 10, 6, validate=True)
+    assert gk.tolist() == [3, 5, 999_999]
