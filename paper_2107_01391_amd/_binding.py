@@ -22,7 +22,7 @@ RS_MAX_ELEMENTS = (1 << 30) - 1
 KINDS = {"u32": RS_KEY_U32, "u64": RS_KEY_U64, "fixed_i64": RS_KEY_FIXED_I64, "str": RS_KEY_STR}
 
 EXPORTED = ["rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_batched_temp_bytes", "rs_sort_batched",
-            "rs_status_string", "rs_last_error"]
+            "rs_status_string", "rs_last_error", "rs_prof_enable", "rs_prof_query"]
 
 
 class RSError(RuntimeError):
@@ -70,6 +70,10 @@ def load_library(path: str | None = None):
     lib.rs_status_string.restype = ctypes.c_char_p
     lib.rs_last_error.argtypes = []
     lib.rs_last_error.restype = ctypes.c_char_p
+    lib.rs_prof_enable.argtypes = [ctypes.c_int]
+    lib.rs_prof_enable.restype = ctypes.c_int
+    lib.rs_prof_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]
+    lib.rs_prof_query.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -135,3 +139,16 @@ def rs_sort_batched(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, d_seg_o
     _check(load_library().rs_sort_batched(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
                                           _ptr(vals_out), _ptr(d_seg_offsets), nseg, total, _ptr(tmp), tmp_bytes,
                                           _stream(stream)))
+
+
+def rs_prof_enable(enable: bool) -> None:
+    """Starts (discarding earlier records) or stops per-kernel event timing."""
+    _check(load_library().rs_prof_enable(int(bool(enable))))
+
+
+def rs_prof_query(name: str) -> tuple[int, float]:
+    """(launches, total milliseconds) of kernel `name` since timing started."""
+    n = ctypes.c_uint64(0)
+    ms = ctypes.c_double(0.0)
+    _check(load_library().rs_prof_query(name.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value

@@ -19,6 +19,17 @@ rs_status validate_keys(const Plan &pl, const void *keys, uint64_t n, void *tmp,
 rs_status run_plan(const Plan &pl, const void *ki, void *ko, const uint32_t *vi, uint32_t *vo, void *tmp,
                    hipStream_t s);
 
+// Kernel timing (rs_prof.h): event pairs around each launch while enabled.
+bool prof_on();
+void *prof_begin(const char *name, hipStream_t s);
+void prof_end(void *token, hipStream_t s);
+#define RS_TIMED(NAME, STREAM, LAUNCH)                                      \
+  do {                                                                      \
+    void *rs_tok_ = ::rs::prof_on() ? ::rs::prof_begin(NAME, STREAM) : nullptr; \
+    LAUNCH;                                                                 \
+    ::rs::prof_end(rs_tok_, STREAM);                                        \
+  } while (0)
+
 // Tile and digit-width choices for a description and size: the autotuner's
 // cached choice when one exists, else the defaults.
 Tuning current_tuning(const rs_key_desc *desc, uint64_t n, bool pairs);

@@ -28,7 +28,7 @@ namespace rs {
 
 // ------------------------------------------------------------------ fill
 
-__global__ void rs_fill(uint4 *__restrict__ p, uint64_t n16, uint32_t value) {
+static __global__ void rs_fill(uint4 *__restrict__ p, uint64_t n16, uint32_t value) {
   const uint4 v = make_uint4(value, value, value, value);
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;

@@ -57,7 +57,7 @@ rs_status launch_fill(void *p, size_t bytes, uint32_t value, hipStream_t stream)
   const uint64_t cap = (uint64_t)cu_count() * 8;
   if (blocks > cap) blocks = cap;
   if (blocks == 0) blocks = 1;
-  hipLaunchKernelGGL(rs_fill, dim3((uint32_t)blocks), dim3(256), 0, stream, (uint4 *)p, n16, value);
+  RS_TIMED("rs_fill", stream, hipLaunchKernelGGL(rs_fill, dim3((uint32_t)blocks), dim3(256), 0, stream, (uint4 *)p, n16, value));
   return check_launch("rs_fill");
 }
 
@@ -86,8 +86,8 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   h.zero16 = pl.status_bytes / 16;
   const size_t lds = (size_t)pl.npasses * pl.bins * 4;
   if (((uintptr_t)keys_in % 16) == 0) {
-    hipLaunchKernelGGL((rs_digit_hash_histogram<K, Digit, 256>), dim3(pl.hist_grid), dim3(256), lds, stream, h,
-                       (const K *)keys_in);
+    RS_TIMED("rs_digit_hash_histogram", stream, hipLaunchKernelGGL((rs_digit_hash_histogram<K, Digit, 256>), dim3(pl.hist_grid), dim3(256), lds, stream, h,
+                       (const K *)keys_in));
   } else {
     return fail(RS_ERR_UNSUPPORTED, "keys_in must be 16-byte aligned");
   }
@@ -107,8 +107,8 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   s.chunks_per_seg = (pl.bins + kScanChunk - 1) / kScanChunk;
   s.nseg_dev = nullptr;
   s.nseg_mul = 1;
-  hipLaunchKernelGGL((rs_cell_scan<kScanBlock, kScanItems>), dim3(s.nseg * s.chunks_per_seg), dim3(kScanBlock), 0,
-                     stream, s);
+  RS_TIMED("rs_cell_scan", stream, hipLaunchKernelGGL((rs_cell_scan<kScanBlock, kScanItems>), dim3(s.nseg * s.chunks_per_seg), dim3(kScanBlock), 0,
+                     stream, s));
   if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
 
   // 4. stable passes; buffer X = output, Y = scratch; pass P-1 writes X
@@ -146,11 +146,11 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
     const dim3 grid((uint32_t)pl.ntiles), blk(256);
     constexpr int KPT = sizeof(K) >= 16 ? 8 : 16;  // LDS staging of one tile: 32 KiB at most
     if (pl.pairs)
-      hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, true, false>), grid, blk, 0, stream, pp, src, dst,
-                         srcv, dstv);
+      RS_TIMED("rs_rank_scatter", stream, hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, true, false>), grid, blk, 0, stream, pp, src, dst,
+                         srcv, dstv));
     else
-      hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, false, false>), grid, blk, 0, stream, pp, src,
-                         dst, nullptr, nullptr);
+      RS_TIMED("rs_rank_scatter", stream, hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, false, false>), grid, blk, 0, stream, pp, src,
+                         dst, nullptr, nullptr));
     if ((st = check_launch("rs_rank_scatter")) != RS_OK) return st;
     src = dst;
     srcv = dstv;
@@ -161,6 +161,10 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
 template <typename K, class Digit>
 static rs_status run_bits(const Plan &pl, const Digit *digits, const void *ki, void *ko, const uint32_t *vi,
                           uint32_t *vo, void *tmp, hipStream_t s) {
+  if constexpr (sizeof(K) >= 16) {  // strings: 27^2 = 729 cells per pass
+    if (pl.bits != 10) return fail(RS_ERR_UNSUPPORTED, "string passes use 10-bit cells");
+    return run_passes<K, Digit, 10>(pl, digits, ki, ko, vi, vo, tmp, s);
+  }
   switch (pl.bits) {
   case 8:
     return run_passes<K, Digit, 8>(pl, digits, ki, ko, vi, vo, tmp, s);
@@ -182,11 +186,11 @@ static rs_status run_literal(const Plan &pl, const void *keys_in, void *keys_out
   const uint64_t cap = (uint64_t)cu_count() * 16;
   if (blocks > cap) blocks = cap;
   if (pl.key.key_bytes == 4)
-    hipLaunchKernelGGL((rs_cell_count<uint32_t, 256>), dim3((uint32_t)blocks), dim3(256), 0, stream,
-                       (const uint32_t *)keys_in, pl.n, pl.literal_cells, counts);
+    RS_TIMED("rs_cell_count", stream, hipLaunchKernelGGL((rs_cell_count<uint32_t, 256>), dim3((uint32_t)blocks), dim3(256), 0, stream,
+                       (const uint32_t *)keys_in, pl.n, pl.literal_cells, counts));
   else
-    hipLaunchKernelGGL((rs_cell_count<uint64_t, 256>), dim3((uint32_t)blocks), dim3(256), 0, stream,
-                       (const uint64_t *)keys_in, pl.n, pl.literal_cells, counts);
+    RS_TIMED("rs_cell_count", stream, hipLaunchKernelGGL((rs_cell_count<uint64_t, 256>), dim3((uint32_t)blocks), dim3(256), 0, stream,
+                       (const uint64_t *)keys_in, pl.n, pl.literal_cells, counts));
   if ((st = check_launch("rs_cell_count")) != RS_OK) return st;
   ScanParams s;
   s.in = counts;
@@ -201,15 +205,15 @@ static rs_status run_literal(const Plan &pl, const void *keys_in, void *keys_out
   s.chunks_per_seg = pl.scan_chunks;
   s.nseg_dev = nullptr;
   s.nseg_mul = 1;
-  hipLaunchKernelGGL((rs_cell_scan<kScanBlock, kScanItems>), dim3(pl.scan_chunks), dim3(kScanBlock), 0, stream, s);
+  RS_TIMED("rs_cell_scan", stream, hipLaunchKernelGGL((rs_cell_scan<kScanBlock, kScanItems>), dim3(pl.scan_chunks), dim3(kScanBlock), 0, stream, s));
   if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
   const uint32_t eb = (pl.literal_cells + 255) / 256;
   if (pl.key.key_bytes == 4)
-    hipLaunchKernelGGL((rs_cell_emit<uint32_t, 256>), dim3(eb), dim3(256), 0, stream, counts, starts,
-                       pl.literal_cells, (uint32_t *)keys_out, pl.n);
+    RS_TIMED("rs_cell_emit", stream, hipLaunchKernelGGL((rs_cell_emit<uint32_t, 256>), dim3(eb), dim3(256), 0, stream, counts, starts,
+                       pl.literal_cells, (uint32_t *)keys_out, pl.n));
   else
-    hipLaunchKernelGGL((rs_cell_emit<uint64_t, 256>), dim3(eb), dim3(256), 0, stream, counts, starts,
-                       pl.literal_cells, (uint64_t *)keys_out, pl.n);
+    RS_TIMED("rs_cell_emit", stream, hipLaunchKernelGGL((rs_cell_emit<uint64_t, 256>), dim3(eb), dim3(256), 0, stream, counts, starts,
+                       pl.literal_cells, (uint64_t *)keys_out, pl.n));
   return check_launch("rs_cell_emit");
 }
 
@@ -244,16 +248,16 @@ rs_status validate_keys(const Plan &pl, const void *keys, uint64_t n, void *tmp,
   const uint64_t space = pl.key.space ? pl.key.space : UINT64_MAX;
   switch (pl.key.key_bytes) {
   case 4:
-    hipLaunchKernelGGL((rs_validate<uint32_t>), dim3((uint32_t)blocks), dim3(256), 0, s, (const uint32_t *)keys, n,
-                       space, bad);
+    RS_TIMED("rs_validate", s, hipLaunchKernelGGL((rs_validate<uint32_t>), dim3((uint32_t)blocks), dim3(256), 0, s, (const uint32_t *)keys, n,
+                       space, bad));
     break;
   case 8:
-    hipLaunchKernelGGL((rs_validate<uint64_t>), dim3((uint32_t)blocks), dim3(256), 0, s, (const uint64_t *)keys, n,
-                       pl.key.kind == RS_KEY_FIXED_I64 && space > (1ull << 63) ? (1ull << 63) : space, bad);
+    RS_TIMED("rs_validate", s, hipLaunchKernelGGL((rs_validate<uint64_t>), dim3((uint32_t)blocks), dim3(256), 0, s, (const uint64_t *)keys, n,
+                       pl.key.kind == RS_KEY_FIXED_I64 && space > (1ull << 63) ? (1ull << 63) : space, bad));
     break;
   default:
-    hipLaunchKernelGGL((rs_validate<Str16>), dim3((uint32_t)blocks), dim3(256), 0, s, (const Str16 *)keys, n, 0,
-                       bad);
+    RS_TIMED("rs_validate", s, hipLaunchKernelGGL((rs_validate<Str16>), dim3((uint32_t)blocks), dim3(256), 0, s, (const Str16 *)keys, n, 0,
+                       bad));
   }
   rs_status st = check_launch("rs_validate");
   if (st != RS_OK) return st;

@@ -13,12 +13,15 @@ import pytest
 from paper_2107_01391_amd import _binding as B
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rs.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))]
 
 
 def _declared():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:rs_status|const char \*)\s*(rs_\w+)\s*\(", text, re.M)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        names |= set(re.findall(r"^\s*(?:rs_status|const char \*)\s*(rs_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 def test_header_declares_the_binding_names():
