@@ -12,6 +12,7 @@ namespace rs {
 
 constexpr int kWave = 64;
 constexpr int kMaxPasses = 16;
+constexpr uint32_t kLdsCountBudget = 48 * 1024;  // bytes of LDS count tables per workgroup
 
 // ------------------------------------------------------------- integer codec
 
@@ -243,21 +244,20 @@ __device__ __forceinline__ void lds_add(uint32_t *p, uint32_t v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Counts value d of every valid lane into LDS table h.  When all valid lanes
-// of the wave hold the same value (skewed cells, padding) one lane adds the
-// whole wave's count, so a hot cell costs one LDS atomic per wave instead of
-// 64 serialised ones.
-__device__ __forceinline__ void wave_count(uint32_t *h, uint32_t d, bool valid) {
-  uint64_t act = ballot(valid);
-  if (act == 0) return;
-  uint32_t first = (uint32_t)__builtin_ctzll(act);
-  uint32_t d0 = __builtin_amdgcn_readlane(d, first);
-  uint64_t same = ballot(valid && d == d0);
-  if (same == act) {
-    if (lane_id() == first) lds_add(h + d0, (uint32_t)__builtin_popcountll(act));
-  } else if (valid) {
-    lds_add(h + d, 1u);
-  }
+// Counts value d into an LDS table held in `copies` copies (a power of two,
+// `cstride` words apart): lane l adds to copy l % copies, so lanes of one
+// wave that hold the same cell (skewed data, padding) serialise at most
+// 64 / copies deep, with no ballot or compare on the way.
+__device__ __forceinline__ void lds_count(uint32_t *table, uint32_t cstride, uint32_t copies, uint32_t d,
+                                          bool valid) {
+  if (valid) lds_add(table + (lane_id() & (copies - 1)) * cstride + d, 1u);
+}
+
+// Copies of an LDS count table that fit `budget` bytes (power of two, <= 8).
+__host__ __device__ inline uint32_t count_copies(uint32_t words, uint32_t budget) {
+  uint32_t c = 8;
+  while (c > 1 && (uint64_t)c * (words + 1) * 4 > budget) c >>= 1;
+  return c;
 }
 
 #endif  // device

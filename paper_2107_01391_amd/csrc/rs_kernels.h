@@ -2,18 +2,23 @@
 //
 //   rs_digit_hash_histogram  the hashing cycle (Section 3.1, eq. (1)): every
 //                            key's cell in every dimension group, counted in
-//                            LDS-private tables, one read of the keys for all
-//                            groups.
+//                            LDS tables, one read of the keys for all groups.
+//   rs_tile_histogram        the same for one group, per tile of keys,
+//                            written so that one flat exclusive scan of the
+//                            table gives every tile's output offset per cell
+//                            (for one array, or for many arrays at once).
 //   rs_cell_scan             the extraction walk's running position (Section
 //                            3.2): exclusive scan of cell counts in
 //                            lexicographic order, single pass with decoupled
-//                            look-back between chunks.
+//                            look-back between chunks; rs_cell_scan_reduce /
+//                            _spine / _down scan a large table in three passes.
 //   rs_rank_scatter          stable emission of one dimension group: ranks
-//                            each key among the tile's keys of its cell,
-//                            looks back over earlier tiles for the cell's
-//                            offset, and writes keys (and values) to their
-//                            final positions through LDS so that stores of
-//                            one cell are contiguous.
+//                            each key among the tile's keys of its cell, gets
+//                            the tile's offset per cell (from the scanned
+//                            table, or for small arrays by look-back over the
+//                            earlier tiles), and writes keys (and values)
+//                            through LDS so that stores of one cell are
+//                            contiguous.
 //   rs_cell_count / rs_cell_emit
 //                            the literal form for keys alone on a small
 //                            space: count every cell of the whole space, then
@@ -33,19 +38,6 @@ static __global__ void rs_fill(uint4 *__restrict__ p, uint64_t n16, uint32_t val
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
 }
-
-// ------------------------------------------------------------- histogram
-
-template <class Digit>
-struct HistParams {
-  Digit digit[kMaxPasses];  // one codec per dimension group (pass)
-  uint32_t npasses;
-  uint32_t stride;          // words per pass row in LDS and in the partials
-  uint64_t n;
-  uint32_t *partials;       // [gridDim.x][npasses][stride], written whole
-  uint4 *zero;              // region cleared on the way (look-back words)
-  uint64_t zero16;          // its size in 16-byte units
-};
 
 // Loads VEC consecutive keys of this thread with one 128-bit load when the
 // whole group is in range (keys are 16-byte aligned), else one by one.
@@ -70,14 +62,28 @@ __device__ __forceinline__ void load_keys(const K *__restrict__ keys, uint64_t e
   }
 }
 
+// ------------------------------------------------------------- histogram
+
+template <class Digit>
+struct HistParams {
+  Digit digit[kMaxPasses];  // one codec per dimension group (pass)
+  uint32_t npasses;
+  uint32_t stride;          // words per pass row
+  uint32_t copies;          // LDS copies of the table (count_copies)
+  uint64_t n;
+  uint32_t *counts;         // [npasses][stride] global counts, zero before launch
+  uint4 *zero;              // region cleared on the way (look-back words)
+  uint64_t zero16;          // its size in 16-byte units
+};
+
 template <typename K, class Digit, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void rs_digit_hash_histogram(const HistParams<Digit> h,
                                                                  const K *__restrict__ keys) {
   constexpr int VEC = 16 / sizeof(K);
-  extern __shared__ uint32_t hist[];  // [npasses][stride]
+  extern __shared__ uint32_t hist[];  // [copies][words + 1]
   const uint32_t t = threadIdx.x;
-  const uint32_t words = h.npasses * h.stride;
-  for (uint32_t i = t; i < words; i += BLOCK) hist[i] = 0;
+  const uint32_t words = h.npasses * h.stride, cstride = words + 1;
+  for (uint32_t i = t; i < h.copies * cstride; i += BLOCK) hist[i] = 0;
 
   // this workgroup's share of the look-back words to clear for later passes
   {
@@ -89,31 +95,160 @@ __global__ __launch_bounds__(BLOCK) void rs_digit_hash_histogram(const HistParam
   }
   __syncthreads();
 
+  constexpr int UNROLL = 4;  // loads in flight per thread before counting
   constexpr uint64_t kStep = (uint64_t)BLOCK * VEC;
-  const uint64_t per = ((h.n + gridDim.x - 1) / gridDim.x + kStep - 1) / kStep * kStep;
+  const uint64_t per = ((h.n + gridDim.x - 1) / gridDim.x + kStep * UNROLL - 1) / (kStep * UNROLL) * (kStep * UNROLL);
   const uint64_t a = (uint64_t)blockIdx.x * per;
   const uint64_t b = a + per < h.n ? a + per : h.n;
-  for (uint64_t base = a; base < b; base += kStep) {
-    K k[VEC];
-    bool valid[VEC];
-    load_keys<K, VEC>(keys, base + (uint64_t)t * VEC, b, k, valid);
-    for (uint32_t p = 0; p < h.npasses; ++p) {
-      uint32_t *row = hist + p * h.stride;
+  for (uint64_t base = a; base < b; base += kStep * UNROLL) {
+    K k[UNROLL][VEC];
+    bool valid[UNROLL][VEC];
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) wave_count(row, valid[q] ? h.digit[p](k[q]) : 0u, valid[q]);
+    for (int u = 0; u < UNROLL; ++u) load_keys<K, VEC>(keys, base + u * kStep + (uint64_t)t * VEC, b, k[u], valid[u]);
+    for (uint32_t p = 0; p < h.npasses; ++p) {
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+        for (int q = 0; q < VEC; ++q)
+          lds_count(hist + p * h.stride, cstride, h.copies, valid[u][q] ? h.digit[p](k[u][q]) : 0u, valid[u][q]);
     }
   }
   __syncthreads();
-  uint32_t *out = h.partials + (uint64_t)blockIdx.x * words;
-  for (uint32_t i = t; i < words; i += BLOCK) out[i] = hist[i];
+  for (uint32_t i = t; i < words; i += BLOCK) {
+    uint32_t c = 0;
+    for (uint32_t r = 0; r < h.copies; ++r) c += hist[r * cstride + i];
+    if (c) atomicAdd(h.counts + i, c);
+  }
+}
+
+// One tile of the batched form, resolved once per sort (rs_seg_tiles) so
+// that the passes read it with one load instead of searching the tables.
+struct alignas(16) TileDesc {
+  uint64_t base;  // first key of the tile's array
+  uint32_t len;   // keys in the array
+  uint32_t j;     // tile index within its array
+  uint32_t nt;    // tiles of the array
+  uint32_t tb;    // tiles of all earlier large arrays
+  uint32_t pad0, pad1;
+};
+
+// Where tile `id` lies and where its per-cell counts go in the flat table.
+// One array: tile id covers keys [id * TILE, ...) and its count of cell d
+// is entry d * ntiles + id.  Many arrays: entry cells * tb + d * nt + j, so
+// the table holds every array's block of [cell][tile] in array order and
+// one exclusive scan over it runs through arrays, then cells, then tiles:
+// exactly the output order.
+struct TileSpan {
+  uint64_t elem0, end, base, limit;  // keys [elem0, end) of the array [base, limit)
+  uint64_t entry0, estride;          // entry of cell d = entry0 + d * estride
+  uint64_t block;                    // first entry of the array's block
+  bool valid;
+};
+
+template <int TILE, bool SEG>
+__device__ __forceinline__ TileSpan tile_span(uint64_t id, uint64_t n, uint32_t ntiles, uint32_t cells,
+                                              const TileDesc *tiles, const uint32_t *ntotal) {
+  TileSpan s;
+  if constexpr (SEG) {
+    s.valid = id < *ntotal;
+    const TileDesc td = s.valid ? tiles[id] : TileDesc{0, 0, 0, 1, 0, 0, 0};
+    s.base = td.base;
+    s.limit = td.base + td.len;
+    s.elem0 = td.base + (uint64_t)td.j * TILE;
+    s.block = (uint64_t)cells * td.tb;
+    s.entry0 = s.block + td.j;
+    s.estride = td.nt;
+  } else {
+    s.valid = id < ntiles;
+    s.base = 0;
+    s.limit = n;
+    s.elem0 = id * TILE;
+    s.block = 0;
+    s.entry0 = id;
+    s.estride = ntiles;
+  }
+  s.end = s.elem0 + TILE < s.limit ? s.elem0 + TILE : s.limit;
+  return s;
+}
+
+template <class Digit>
+struct TileHistParams {
+  Digit digit;
+  uint32_t cells;    // cells of this pass's group
+  uint32_t ntiles;   // one array: its tiles
+  uint32_t copies;   // LDS copies per tile table
+  uint64_t n;        // one array: its length
+  uint32_t *counts;  // flat table (see tile_span)
+  const TileDesc *tiles;   // many arrays: resolved tiles
+  const uint32_t *ntotal;  // many arrays: tiles in use
+};
+
+// Per-tile counts of one dimension group; each workgroup takes TPW
+// consecutive tiles.
+template <typename K, class Digit, int BLOCK, int TPW, int TILE, bool SEG>
+__global__ __launch_bounds__(BLOCK) void rs_tile_histogram(const TileHistParams<Digit> h, const K *__restrict__ keys) {
+  extern __shared__ uint32_t cnt[];  // [TPW][copies][cells + 1]
+  __shared__ uint64_t s_entry0[TPW], s_estride[TPW];
+  const uint32_t t = threadIdx.x;
+  const uint32_t cstride = h.cells + 1, tstride = h.copies * cstride;
+  for (uint32_t i = t; i < TPW * tstride; i += BLOCK) cnt[i] = 0;
+  __syncthreads();
+  const uint64_t t0 = (uint64_t)blockIdx.x * TPW;
+  for (uint32_t jj = 0; jj < (uint32_t)TPW; ++jj) {
+    const TileSpan sp = tile_span<TILE, SEG>(t0 + jj, h.n, h.ntiles, h.cells, h.tiles, h.ntotal);
+    if (t == 0) {
+      s_entry0[jj] = sp.valid ? sp.entry0 : ~0ull;
+      s_estride[jj] = sp.estride;
+    }
+    if (!sp.valid) continue;  // uniform
+    uint32_t *row = cnt + jj * tstride;
+    if constexpr (!SEG) {
+      // one array: tiles start at multiples of TILE, so 128-bit loads line up
+      constexpr int VEC = 16 / sizeof(K);
+      constexpr int UNROLL = TILE / (BLOCK * VEC) < 4 ? TILE / (BLOCK * VEC) : 4;
+      for (uint64_t base = sp.elem0; base < sp.end; base += (uint64_t)BLOCK * VEC * UNROLL) {
+        K k[UNROLL][VEC];
+        bool valid[UNROLL][VEC];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+          load_keys<K, VEC>(keys, base + (uint64_t)(u * BLOCK + t) * VEC, sp.end, k[u], valid[u]);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+          for (int q = 0; q < VEC; ++q)
+            lds_count(row, cstride, h.copies, valid[u][q] ? h.digit(k[u][q]) : 0u, valid[u][q]);
+      }
+    } else {
+      constexpr int KPT = TILE / BLOCK;  // arrays start anywhere: one key per lane per load
+      K k[KPT];
+#pragma unroll
+      for (int r = 0; r < KPT; ++r) {
+        const uint64_t e = sp.elem0 + (uint64_t)r * BLOCK + t;
+        k[r] = e < sp.end ? keys[e] : K{};
+      }
+#pragma unroll
+      for (int r = 0; r < KPT; ++r) {
+        const bool valid = sp.elem0 + (uint64_t)r * BLOCK + t < sp.end;
+        lds_count(row, cstride, h.copies, valid ? h.digit(k[r]) : 0u, valid);
+      }
+    }
+  }
+  __syncthreads();
+  // TPW consecutive entries per cell when the tiles are one array's
+  for (uint32_t i = t; i < h.cells * TPW; i += BLOCK) {
+    const uint32_t d = i / TPW, jj = i % TPW;
+    const uint64_t e0 = s_entry0[jj];
+    if (e0 == ~0ull) continue;
+    uint32_t c = 0;
+    for (uint32_t r = 0; r < h.copies; ++r) c += cnt[jj * tstride + r * cstride + d];
+    h.counts[e0 + (uint64_t)d * s_estride[jj]] = c;
+  }
 }
 
 // ------------------------------------------------------------- cell scan
 
 struct ScanParams {
-  const uint32_t *in;       // counts: [nparts][nseg][stride]; summed over parts
-  uint64_t part_stride;     // words between part tables
-  uint32_t nparts;
+  const uint32_t *in;       // counts: [nseg][stride]
   uint32_t nseg;            // independent scans
   uint32_t cells;           // cells per scan
   uint32_t stride;          // words between consecutive scans (in and out)
@@ -140,12 +275,7 @@ __global__ __launch_bounds__(BLOCK) void rs_cell_scan(const ScanParams s) {
   const uint32_t lo = cc * CH;
   const uint32_t hi = lo + CH < s.cells ? lo + CH : s.cells;
   const uint64_t row = (uint64_t)seg * s.stride;
-  for (uint32_t i = t; i < CH; i += BLOCK) {
-    uint32_t cell = lo + i, v = 0;
-    if (cell < hi)
-      for (uint32_t g = 0; g < s.nparts; ++g) v += s.in[g * s.part_stride + row + cell];
-    vals[i] = v;
-  }
+  for (uint32_t i = t; i < CH; i += BLOCK) vals[i] = lo + i < hi ? s.in[row + lo + i] : 0u;
   __syncthreads();
   const uint32_t total = block_exclusive_scan<BLOCK>(vals, CH, wsum);
   if (t == 0) {
@@ -163,6 +293,75 @@ __global__ __launch_bounds__(BLOCK) void rs_cell_scan(const ScanParams s) {
   __syncthreads();
   const uint32_t excl = s_excl;
   for (uint32_t i = t; lo + i < hi; i += BLOCK) s.out[row + lo + i] = vals[i] + excl;
+}
+
+// Three-pass exclusive scan of a large table (no chain between workgroups):
+// chunk sums, a one-workgroup scan of the sums, then each chunk rescanned
+// from its base.  In place (out == in) is allowed.
+// The table length is `count`, or when count_dev is set *count_dev * count_mul
+// (a size known only on the device); chunks past it do nothing.
+__device__ __forceinline__ uint64_t scan_count(uint64_t count, const uint32_t *count_dev, uint32_t count_mul) {
+  return count_dev ? (uint64_t)*count_dev * count_mul : count;
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void rs_cell_scan_reduce(const uint32_t *__restrict__ in, uint64_t count_host,
+                                                             const uint32_t *count_dev, uint32_t count_mul,
+                                                             uint32_t *__restrict__ sums) {
+  const uint64_t count = scan_count(count_host, count_dev, count_mul);
+  const uint64_t lo = (uint64_t)blockIdx.x * BLOCK * ITEMS;
+  if (lo >= count) return;  // uniform
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint64_t e = lo + (uint64_t)i * BLOCK + threadIdx.x;
+    s += e < count ? in[e] : 0u;
+  }
+  __shared__ uint32_t part[BLOCK / kWave];
+  s = wave_sum(s);
+  if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t tot = 0;
+    for (int w = 0; w < BLOCK / kWave; ++w) tot += part[w];
+    sums[blockIdx.x] = tot;
+  }
+}
+
+template <int BLOCK, int CHUNK>
+__global__ __launch_bounds__(BLOCK) void rs_cell_scan_spine(uint32_t *__restrict__ sums, uint64_t count_host,
+                                                            const uint32_t *count_dev, uint32_t count_mul) {
+  const uint32_t nchunks = (uint32_t)((scan_count(count_host, count_dev, count_mul) + CHUNK - 1) / CHUNK);
+  __shared__ uint32_t buf[BLOCK];
+  __shared__ uint32_t wsum[BLOCK / kWave];
+  uint32_t run = 0;
+  for (uint32_t base = 0; base < nchunks; base += BLOCK) {
+    const uint32_t i = base + threadIdx.x;
+    buf[threadIdx.x] = i < nchunks ? sums[i] : 0u;
+    __syncthreads();
+    const uint32_t tot = block_exclusive_scan<BLOCK>(buf, BLOCK, wsum);
+    if (i < nchunks) sums[i] = buf[threadIdx.x] + run;
+    run += tot;
+    __syncthreads();
+  }
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void rs_cell_scan_down(const uint32_t *in, uint64_t count_host,
+                                                           const uint32_t *count_dev, uint32_t count_mul,
+                                                           const uint32_t *__restrict__ sums, uint32_t *out) {
+  constexpr uint32_t CH = BLOCK * ITEMS;
+  __shared__ uint32_t vals[CH];
+  __shared__ uint32_t wsum[BLOCK / kWave];
+  const uint64_t count = scan_count(count_host, count_dev, count_mul);
+  const uint64_t lo = (uint64_t)blockIdx.x * CH;
+  if (lo >= count) return;  // uniform
+  for (uint32_t i = threadIdx.x; i < CH; i += BLOCK) vals[i] = lo + i < count ? in[lo + i] : 0u;
+  __syncthreads();
+  block_exclusive_scan<BLOCK>(vals, CH, wsum);
+  const uint32_t base = sums[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < CH; i += BLOCK)
+    if (lo + i < count) out[lo + i] = vals[i] + base;
 }
 
 // ------------------------------------------------- tile ranking helpers
@@ -217,27 +416,38 @@ __device__ __forceinline__ void cell_totals(uint32_t (&wcnt)[WAVES][BINS], uint3
 
 // ------------------------------------------------------ rank and scatter
 
+// How a tile finds its output offsets:
+//   kChained       one (small) array; decoupled look-back over the earlier
+//                  tiles, tile ids from an atomic counter so that every
+//                  tile's predecessors are already running when it waits
+//   kPrescanned    one array; offsets from the scanned per-tile table
+//   kPrescannedSeg many arrays; offsets from the scanned per-tile table
+enum PassMode { kChained = 0, kPrescanned = 1, kPrescannedSeg = 2 };
+
 template <class Digit>
 struct PassParams {
   Digit digit;
   uint32_t bins;                // cells of this pass's group
   uint64_t n;                   // one array: its length
-  const uint32_t *digit_start;  // exclusive scan of the pass's cell counts
-  uint64_t dstride;             // segmented: words between segments' scans
-  uint32_t *status;             // look-back words [tiles][bins], zero
-  uint32_t *tile_counter;       // zero before launch
-  // segmented (batched) form; unused for one array
-  const uint64_t *seg_off;      // [nseg + 1]
-  const uint32_t *tile_base;    // [nlarge + 1] first tile of each large array
-  const uint32_t *large_ids;    // [nlarge] index of each large array
-  const uint32_t *nlarge;       // device scalar
+  uint32_t ntiles;              // one array: its tiles
+  const uint32_t *digit_start;  // kChained: exclusive scan of the pass's counts
+  uint32_t *status;             // kChained: look-back words [tiles][bins], zero
+  uint32_t *tile_counter;       // kChained: zero before launch
+  const uint32_t *tile_offsets; // prescanned: the scanned per-tile table
+  const TileDesc *tiles;        // kPrescannedSeg: resolved tiles
+  const uint32_t *ntotal;       // kPrescannedSeg: tiles in use
 };
 
 // One tile = BLOCK * KPT consecutive keys.  Wave w owns keys
 // [w * 64 * KPT, (w + 1) * 64 * KPT) of the tile, 64 per round, so the
 // order (wave, round, lane) is the input order and every rank below is the
 // number of earlier keys of the same cell: the sort is stable.
-template <typename K, class Digit, int BITS, int BLOCK, int KPT, bool PAIRS, bool SEG>
+//
+// Prescanned tiles do not depend on each other, so their order is chosen
+// for locality: consecutive tiles run on the same XCD (workgroup b runs on
+// XCD b % 8), where the partial cache lines of neighbouring tiles' output
+// runs meet in one L2.  The grid is a multiple of 8; extra workgroups exit.
+template <typename K, class Digit, int BITS, int BLOCK, int KPT, bool PAIRS, int MODE>
 __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit> p, const K *__restrict__ kin,
                                                          K *__restrict__ kout, const uint32_t *__restrict__ vin,
                                                          uint32_t *__restrict__ vout) {
@@ -251,51 +461,26 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
   __shared__ uint32_t tstart[BINS];       // tile-local start of each cell
   __shared__ uint32_t gdelta[BINS];       // output index - tile-local index
   __shared__ uint32_t wsum[WAVES];
-  __shared__ uint64_t s_tile, s_first, s_elem0, s_end, s_seg, s_row;
+  __shared__ uint64_t s_id;
 
   const uint32_t t = threadIdx.x, lane = t % kWave, wave = t / kWave;
   K *stage_k = reinterpret_cast<K *>(stage_raw);
   uint32_t *stage_v = reinterpret_cast<uint32_t *>(stage_raw);
 
   for (uint32_t i = t; i < (uint32_t)(WAVES * BINS); i += BLOCK) (&wcnt[0][0])[i] = 0;
-  if (t == 0) {
-    const uint64_t tile = atomicAdd(p.tile_counter, 1u);
-    if constexpr (!SEG) {
-      s_tile = tile;
-      s_first = 0;
-      s_elem0 = tile * TILE;
-      s_end = s_elem0 + TILE < p.n ? s_elem0 + TILE : p.n;
-      s_seg = 0;
-      s_row = 0;
-    } else {
-      const uint32_t L = *p.nlarge;
-      if (tile >= p.tile_base[L]) {
-        s_tile = ~0ull;
-      } else {
-        uint32_t lo = 0, hi = L;  // last j with tile_base[j] <= tile
-        while (hi - lo > 1) {
-          uint32_t mid = (lo + hi) / 2;
-          if (p.tile_base[mid] <= tile) lo = mid;
-          else hi = mid;
-        }
-        const uint32_t sid = p.large_ids[lo];
-        const uint64_t sb = p.seg_off[sid], se = p.seg_off[sid + 1];
-        s_tile = tile;
-        s_first = p.tile_base[lo];
-        s_elem0 = sb + (tile - s_first) * TILE;
-        s_end = s_elem0 + TILE < se ? s_elem0 + TILE : se;
-        s_seg = sid;
-        s_row = lo;
-      }
-    }
+  uint64_t id;
+  if constexpr (MODE == kChained) {
+    if (t == 0) s_id = atomicAdd(p.tile_counter, 1u);
+    __syncthreads();
+    id = s_id;
+  } else {
+    const uint64_t per8 = gridDim.x / 8;
+    id = (blockIdx.x % 8) * per8 + blockIdx.x / 8;
   }
-  __syncthreads();
-  const uint64_t tile = s_tile;
-  if (SEG && tile == ~0ull) return;
-  const uint64_t first = s_first, elem0 = s_elem0, end = s_end;
-  const uint64_t out_base = SEG ? p.seg_off[s_seg] : 0;
-  const uint64_t limit = SEG ? p.seg_off[s_seg + 1] : p.n;  // no store leaves the array
-  const uint32_t *dstart = SEG ? p.digit_start + s_row * p.dstride : p.digit_start;
+  const TileSpan sp = tile_span<TILE, MODE == kPrescannedSeg>(id, p.n, p.ntiles, p.bins, p.tiles, p.ntotal);
+  if (!sp.valid) return;  // uniform
+  const uint64_t elem0 = sp.elem0, end = sp.end, out_base = sp.base, limit = sp.limit;
+  const bool first_tile = id == 0;
 
   // ---- load: keys and values of this thread, striped by rounds
   K k[KPT];
@@ -307,6 +492,7 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
     k[r] = e < end ? kin[e] : K{};
     if constexpr (PAIRS) v[r] = e < end ? vin[e] : 0u;
   }
+  if constexpr (MODE != kChained) __syncthreads();  // wcnt cleared
 
   // ---- rank inside the wave: counts of the same cell in earlier rounds
   // (per-wave LDS counters) plus same-cell lanes below in this round.
@@ -317,38 +503,47 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
   wave_rank<BITS, KPT>(p.digit, k, nvalid, wcnt[wave], dg, rk);
   __syncthreads();
 
-  // ---- per cell: tile count, per-wave offsets, publish the tile's count
+  // ---- per cell: tile count, per-wave offsets (chained: publish it)
   uint32_t tot[CPT];
   cell_totals<BLOCK, WAVES, BINS, CPT>(wcnt, tstart, p.bins, tot);
+  if constexpr (MODE == kChained) {
 #pragma unroll
-  for (int j = 0; j < CPT; ++j) {
-    const uint32_t d = t + j * BLOCK;
-    if (d < p.bins) publish(p.status + tile * p.bins + d, (tile == first ? kFlagPrefix : kFlagAgg) | tot[j]);
+    for (int c = 0; c < CPT; ++c) {
+      const uint32_t d = t + c * BLOCK;
+      if (d < p.bins) publish(p.status + id * p.bins + d, (first_tile ? kFlagPrefix : kFlagAgg) | tot[c]);
+    }
   }
   __syncthreads();
   block_exclusive_scan<BLOCK>(tstart, p.bins, wsum);
 
-  // ---- look back over earlier tiles of this array for each cell's offset
-#pragma unroll
-  for (int j = 0; j < CPT; ++j) {
-    const uint32_t d = t + j * BLOCK;
-    if (d < p.bins) {
-      uint32_t excl = 0;
-      if (tile != first) {
-        excl = look_back(p.status + d, tile, first, p.bins);
-        publish(p.status + tile * p.bins + d, kFlagPrefix | (excl + tot[j]));
-      }
-      gdelta[d] = dstart[d] + excl - tstart[d];
-    }
-  }
-
   // ---- place keys in LDS at their tile-local sorted index
 #pragma unroll
   for (int r = 0; r < KPT; ++r) {
-    const bool valid = wbase + (uint64_t)r * kWave < end;
+    const bool valid = (uint32_t)r * kWave + lane < nvalid;
     const uint32_t lpos = tstart[dg[r]] + wcnt[wave][dg[r]] + rk[r];
     rk[r] = lpos;
     if (valid) stage_k[lpos] = k[r];
+  }
+
+  // ---- each cell's output offset for this tile, relative to its array
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) {
+    const uint32_t d = t + c * BLOCK;
+    if (d < p.bins) {
+      if constexpr (MODE == kChained) {
+        uint32_t excl = 0;
+        if (!first_tile) {
+          excl = look_back(p.status + d, id, 0, p.bins);
+          publish(p.status + id * p.bins + d, kFlagPrefix | (excl + tot[c]));
+        }
+        gdelta[d] = p.digit_start[d] + excl - tstart[d];
+      } else {
+        // wraps consistently in 32 bits: the difference is below 2^30
+        uint32_t rel = p.tile_offsets[sp.entry0 + (uint64_t)d * sp.estride];
+        if constexpr (MODE == kPrescannedSeg) rel -= p.tile_offsets[sp.block];
+        gdelta[d] = rel - tstart[d];
+      }
+    }
   }
   __syncthreads();
 
@@ -356,12 +551,12 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
   // output addresses
   const uint32_t count = (uint32_t)(end - elem0);
 #pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const uint32_t i = t + j * BLOCK;
+  for (int r = 0; r < KPT; ++r) {
+    const uint32_t i = t + r * BLOCK;
     if (i < count) {
       const K key = stage_k[i];
       const uint32_t d = p.digit(key);
-      dg[j] = d;
+      dg[r] = d;
       const uint64_t at = out_base + gdelta[d] + i;
       if (at < limit) kout[at] = key;
     }
@@ -370,12 +565,12 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < KPT; ++r)
-      if (wbase + (uint64_t)r * kWave < end) stage_v[rk[r]] = v[r];
+      if ((uint32_t)r * kWave + lane < nvalid) stage_v[rk[r]] = v[r];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < KPT; ++j) {
-      const uint32_t i = t + j * BLOCK;
-      const uint64_t at = out_base + gdelta[dg[j]] + i;
+    for (int r = 0; r < KPT; ++r) {
+      const uint32_t i = t + r * BLOCK;
+      const uint64_t at = out_base + gdelta[dg[r]] + i;
       if (i < count && at < limit) vout[at] = stage_v[i];
     }
   }

@@ -1,0 +1,122 @@
+// rs_passes.h -- launch sequence of one prescanned pass (reduce-then-scan):
+//
+//   rs_tile_histogram   per-tile counts of the pass's cells, flat table
+//   rs_cell_scan_*      one exclusive scan of the whole table
+//   rs_rank_scatter     stable scatter with offsets read from the table
+//
+// No tile waits on another: on MI355X every serialised global round trip
+// inside a tile costs the latency of a saturated HBM queue, so passes avoid
+// chains between tiles entirely.  The same sequence serves one array and
+// many arrays (SEG), whose tables are laid out so that one scan covers all.
+#pragma once
+
+#include <string.h>
+
+#include "rs_internal.h"
+#include "rs_kernels.h"
+
+namespace rs {
+
+constexpr int kTilesPerHistBlock = 8;
+
+template <typename K, class Digit, int BITS, bool SEG>
+rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const K *src, K *dst,
+                          const uint32_t *srcv, uint32_t *dstv, uint64_t n, uint64_t ntiles_bound,
+                          uint32_t *table, uint32_t *sums, const TileDesc *tiles, const uint32_t *ntotal,
+                          hipStream_t stream) {
+  constexpr int KPT = sizeof(K) >= 16 ? 8 : 16;  // LDS staging of one tile: 32 KiB at most
+  constexpr int TILE = 256 * KPT;
+  constexpr int TPW = kTilesPerHistBlock;
+  rs_status st;
+  const uint64_t count = (uint64_t)cells * ntiles_bound;
+  const uint32_t nchunks = (uint32_t)((count + kBigScanChunk - 1) / kBigScanChunk);
+
+  TileHistParams<Digit> th;
+  th.digit = digit;
+  th.cells = cells;
+  th.ntiles = (uint32_t)ntiles_bound;
+  th.copies = count_copies(cells * TPW, kLdsCountBudget);
+  th.n = n;
+  th.counts = table;
+  th.tiles = tiles;
+  th.ntotal = ntotal;
+  const size_t lds = (size_t)TPW * th.copies * (cells + 1) * 4;
+  RS_TIMED("rs_tile_histogram", stream,
+           hipLaunchKernelGGL((rs_tile_histogram<K, Digit, 256, TPW, TILE, SEG>),
+                              dim3((uint32_t)((ntiles_bound + TPW - 1) / TPW)), dim3(256), lds, stream, th, src));
+  if ((st = check_launch("rs_tile_histogram")) != RS_OK) return st;
+
+  const uint32_t *cdev = SEG ? ntotal : nullptr;
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan_reduce<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
+                              stream, table, count, cdev, cells, sums));
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan_spine<1024, kBigScanChunk>), dim3(1), dim3(1024), 0, stream, sums, count,
+                              cdev, cells));
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
+                              stream, table, count, cdev, cells, sums, table));
+  if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
+
+  PassParams<Digit> pp;
+  memset(&pp, 0, sizeof pp);
+  pp.digit = digit;
+  pp.bins = cells;
+  pp.n = n;
+  pp.ntiles = (uint32_t)ntiles_bound;
+  pp.tile_offsets = table;
+  pp.tiles = tiles;
+  pp.ntotal = ntotal;
+  constexpr int MODE = SEG ? kPrescannedSeg : kPrescanned;
+  const dim3 grid((uint32_t)((ntiles_bound + 7) / 8 * 8)), blk(256);
+  if (pairs)
+    RS_TIMED("rs_rank_scatter", stream,
+             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, true, MODE>), grid, blk, 0, stream, pp,
+                                src, dst, srcv, dstv));
+  else
+    RS_TIMED("rs_rank_scatter", stream,
+             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, false, MODE>), grid, blk, 0, stream, pp,
+                                src, dst, nullptr, nullptr));
+  return check_launch("rs_rank_scatter");
+}
+
+// Runs passes [0, P) (least significant first) from keys_in to keys_out,
+// ping-ponging through alt; the last pass writes keys_out.  When the input
+// is the output and P is odd, the input is first copied to alt.
+template <typename K, class Digit, int BITS, bool SEG>
+rs_status prescanned_passes(const Plan &p, const Digit *digits, uint32_t P, const void *keys_in, void *keys_out,
+                            const uint32_t *vals_in, uint32_t *vals_out, void *alt_keys, uint32_t *alt_vals,
+                            uint64_t n, uint64_t ntiles_bound, uint32_t *table, uint32_t *sums,
+                            const TileDesc *tiles, const uint32_t *ntotal, hipStream_t stream) {
+  const bool pairs = vals_in != nullptr;
+  K *X = (K *)keys_out;
+  K *Y = (K *)alt_keys;
+  uint32_t *XV = vals_out;
+  uint32_t *YV = alt_vals;
+  const K *src = (const K *)keys_in;
+  const uint32_t *srcv = vals_in;
+  const bool odd = P % 2 == 1;
+  if (odd && keys_in == keys_out) {
+    if (hipMemcpyAsync(Y, keys_in, n * p.key.key_bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return fail(RS_ERR_HIP, "hipMemcpyAsync");
+    src = Y;
+  }
+  if (pairs && odd && vals_in == vals_out) {
+    if (hipMemcpyAsync(YV, vals_in, n * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return fail(RS_ERR_HIP, "hipMemcpyAsync");
+    srcv = YV;
+  }
+  for (uint32_t i = 0; i < P; ++i) {
+    const bool to_x = ((P - 1 - i) % 2) == 0;
+    K *dst = to_x ? X : Y;
+    uint32_t *dstv = to_x ? XV : YV;
+    rs_status st = prescanned_pass<K, Digit, BITS, SEG>(digits[i], p.pass_cells[i], pairs, src, dst, srcv, dstv, n,
+                                                         ntiles_bound, table, sums, tiles, ntotal, stream);
+    if (st != RS_OK) return st;
+    src = dst;
+    srcv = dstv;
+  }
+  return RS_OK;
+}
+
+}  // namespace rs

@@ -212,17 +212,16 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
   p.tile = p.block * p.kpt;
   p.ntiles = (n + p.tile - 1) / p.tile;
 
-  // histogram grid: enough workgroups to fill 256 CUs, partial tables capped
+  // histogram grid: enough workgroups to fill 256 CUs
   const uint64_t words = (uint64_t)p.npasses * p.bins;
   uint64_t g = (n + 16383) / 16384;
-  uint64_t cap = (2u << 20) / (words ? words : 1);
-  if (cap < 1) cap = 1;
   if (g > 1024) g = 1024;
-  if (g > cap) g = cap;
   if (g < 1) g = 1;
   p.hist_grid = (uint32_t)g;
+  p.hist_copies = count_copies((uint32_t)words, kLdsCountBudget);
 
-  // scratch layout
+  p.prescanned = !p.literal && n >= tune.prescan_min_n;
+
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t at = off;
@@ -236,18 +235,79 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     p.off_ctrl = take(((size_t)p.scan_chunks + 1) * 4);
     p.ctrl_bytes = off - p.off_counts;
     p.off_starts = take((size_t)p.literal_cells * 4);
+  } else if (p.prescanned) {
+    p.off_keys_alt = take((size_t)n * k.key_bytes);
+    if (pairs) p.off_vals_alt = take((size_t)n * 4);
+    const uint64_t entries = (uint64_t)p.bins * p.ntiles;
+    p.scan_chunks = (uint32_t)((entries + kBigScanChunk - 1) / kBigScanChunk);
+    p.off_table = take(entries * 4);
+    p.off_sums = take((size_t)p.scan_chunks * 4);
   } else {
     p.off_keys_alt = take((size_t)n * k.key_bytes);
     if (pairs) p.off_vals_alt = take((size_t)n * 4);
-    p.off_partials = take((size_t)p.hist_grid * words * 4);
     p.off_dstart = take(words * 4);
     p.status_bytes = align_up((size_t)p.npasses * p.ntiles * p.bins * 4, 256);
     p.off_status = take(p.status_bytes);
+    // control: [0, P) tile counters, P scan counter, P+1.. scan chunk status,
+    // then the global count table [P][bins]
     p.scan_chunks = p.npasses * ((p.bins + kScanChunk - 1) / kScanChunk);
-    p.ctrl_bytes = align_up(((size_t)p.npasses + 1 + p.scan_chunks) * 4, 256);
-    p.off_ctrl = take(p.ctrl_bytes);
+    p.off_ctrl = take(((size_t)p.npasses + 1 + p.scan_chunks + words) * 4);
+    p.ctrl_bytes = off - p.off_ctrl;
   }
   p.total = off ? off : 256;
+  return RS_OK;
+}
+
+rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint32_t nseg, bool own_alt,
+                          SegLayout *Lp, std::string *why) {
+  SegLayout &L = *Lp;
+  L = SegLayout();
+  if (nseg == 0) {
+    *why = "nseg must be at least 1";
+    return RS_ERR_BAD_DESC;
+  }
+  if (total >= (1ull << 40)) {
+    *why = "total must be below 2^40";
+    return RS_ERR_UNSUPPORTED;
+  }
+  const uint32_t kb = p.key.key_bytes;
+  L.npasses = npasses;
+  L.total = total;
+  L.nseg = nseg;
+  L.own_alt = own_alt;
+  L.tile = kb >= 16 ? 2048 : 4096;
+  L.small_max = L.tile;
+  // a large array spans more than one tile, so there are at most
+  // total / tile of them, each adding at most one partial tile
+  const uint64_t full = (total + L.tile - 1) / L.tile;
+  L.tiles_bound = full + (nseg < total / L.tile ? nseg : total / L.tile);
+  if (L.tiles_bound == 0) L.tiles_bound = 1;
+  if (L.tiles_bound >= (1ull << 31)) {
+    *why = "too many tiles";
+    return RS_ERR_UNSUPPORTED;
+  }
+  const uint64_t cus = 256;
+  L.small_grid = (uint32_t)(nseg < cus * 8 ? nseg : cus * 8);
+
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  if (own_alt) {
+    L.off_alt_keys = take(total * kb);
+    if (p.pairs) L.off_alt_vals = take(total * 4);
+  }
+  L.off_ctrl = take(3 * 4);
+  L.off_large_ids = take((size_t)nseg * 4);
+  L.off_tile_base = take(((size_t)nseg + 1) * 4);
+  L.off_small_ids = take((size_t)nseg * 4);
+  L.off_tiles = take(L.tiles_bound * 32);
+  const uint64_t entries = (uint64_t)p.bins * L.tiles_bound;
+  L.off_table = take(entries * 4);
+  L.off_sums = take((entries + kBigScanChunk - 1) / kBigScanChunk * 4);
+  L.bytes = off;
   return RS_OK;
 }
 

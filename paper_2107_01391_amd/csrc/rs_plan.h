@@ -1,10 +1,19 @@
 // rs_plan.h -- host planner of the gfx950 Recombinant Sort path.
 //
 // Turns a key description into the passes of the hot path: how the N digit
-// dimensions are grouped (one count space per group, least significant group
-// sorted first so that the stable passes compose to the lexicographic order
-// of the whole space), which codec extracts a group's cell, the tile shape
-// of the kernels, and the layout of the caller's scratch buffer.
+// dimensions are grouped (one count space per group), which codec extracts a
+// group's cell, the order of the passes, the tile shape of the kernels, and
+// the layout of the caller's scratch buffer.
+//
+// A single array is sorted in one of three ways:
+//   literal     keys alone on a small integer space: the whole space is one
+//               count space (count, scan, emit rebuilt keys);
+//   chained     stable passes over the groups, least significant first, each
+//               pass one kernel whose tiles chain their offsets by look-back
+//               (few launches: small arrays);
+//   prescanned  the same passes, each as per-tile counts, one flat scan and
+//               a scatter whose offsets are read from the scanned table (no
+//               chain between tiles: large arrays).
 #pragma once
 
 #include <stddef.h>
@@ -12,7 +21,7 @@
 
 #include <string>
 
-#include "../../include/rs.h"
+#include "rs.h"
 #include "rs_device.h"
 
 namespace rs {
@@ -28,8 +37,28 @@ struct KeyInfo {
 };
 
 struct Tuning {
-  uint32_t digit_bits = 8;   // target width of a pass (power-of-two bases)
-  uint32_t max_cells = 1024; // largest count space of one pass (other bases)
+  uint32_t digit_bits = 8;       // target width of a pass (power-of-two bases)
+  uint32_t max_cells = 1024;     // largest count space of one pass (other bases)
+  uint64_t prescan_min_n = 3ull << 20;  // single arrays from this size use prescanned passes
+};
+
+// Scratch layout of the segmented form over `nseg` arrays holding `total`
+// keys, sorted by passes [0, npasses) of a parent plan (least significant
+// first).  Offsets are relative to the start of the segmented region.
+struct SegLayout {
+  uint32_t npasses = 0;
+  uint64_t total = 0;
+  uint32_t nseg = 0;
+  uint32_t tile = 4096, small_max = 4096;
+  uint64_t tiles_bound = 0;  // large-array tiles, at most
+  uint32_t small_grid = 1;
+  bool own_alt = false;
+  size_t off_alt_keys = 0, off_alt_vals = 0;
+  size_t off_ctrl = 0;  // nlarge, nsmall, tiles in use
+  size_t off_large_ids = 0, off_tile_base = 0, off_small_ids = 0;
+  size_t off_tiles = 0;  // TileDesc per tile id
+  size_t off_table = 0, off_sums = 0;  // per-tile count table and its chunk sums
+  size_t bytes = 0;
 };
 
 struct Plan {
@@ -37,9 +66,10 @@ struct Plan {
   bool pairs = false;
   bool literal = false;      // keys only, whole space counted at once
   uint32_t literal_cells = 0;
+  bool prescanned = false;   // passes without look-back
 
   DigitMode mode = kModePow2;
-  uint32_t npasses = 0;
+  uint32_t npasses = 0;      // passes in least-significant-first order
   uint32_t bins = 0;         // cells of the widest pass
   uint32_t bits = 8;         // kernel variant: 8, 10 or 11 bits of cell index
   uint32_t pass_cells[kMaxPasses] = {};
@@ -50,23 +80,30 @@ struct Plan {
 
   uint32_t block = 256, kpt = 16, tile = 4096;
   uint64_t n = 0, ntiles = 0;
-  uint32_t hist_grid = 1;
+  uint32_t hist_grid = 1, hist_copies = 1;
 
   // scratch layout (byte offsets into tmp)
-  size_t off_keys_alt = 0, off_vals_alt = 0, off_partials = 0, off_dstart = 0, off_status = 0;
+  size_t off_keys_alt = 0, off_vals_alt = 0, off_dstart = 0, off_status = 0;
   size_t off_ctrl = 0, ctrl_bytes = 0, status_bytes = 0;
   size_t off_counts = 0, off_starts = 0;
+  size_t off_table = 0, off_sums = 0;  // prescanned: per-tile counts, chunk sums
+  uint32_t scan_chunks = 0;            // chunks of the cell scan
+  SegLayout seg;                       // batched form
   size_t total = 0;
-  uint32_t scan_chunks = 0;  // chunks of the cell scan
 };
 
 rs_status key_info(const rs_key_desc *desc, KeyInfo *ki, std::string *why);
 rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tuning &tune, Plan *plan,
                     std::string *why);
+// Layout of the segmented form for passes [0, npasses) of `p`.
+rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint32_t nseg, bool own_alt,
+                          SegLayout *L, std::string *why);
 
 constexpr uint32_t kScanBlock = 256;
 constexpr uint32_t kScanItems = 8;
 constexpr uint32_t kScanChunk = kScanBlock * kScanItems;
+constexpr uint32_t kBigScanItems = 16;
+constexpr uint32_t kBigScanChunk = kScanBlock * kBigScanItems;
 constexpr uint32_t kLiteralMaxCells = 1u << 24;
 
 }  // namespace rs

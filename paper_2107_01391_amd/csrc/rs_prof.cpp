@@ -1,5 +1,5 @@
 // rs_prof.cpp -- event-pair timing of the library's kernel launches.
-#include "../../include/rs_prof.h"
+#include "rs_prof.h"
 
 #include <string.h>
 

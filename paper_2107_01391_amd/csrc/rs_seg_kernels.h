@@ -5,11 +5,12 @@
 //   rs_seg_plan       one workgroup: splits the arrays into small ones (sorted
 //                     whole on chip) and large ones, and numbers the large
 //                     arrays' tiles (device side: no host round trip)
+//   rs_seg_tiles      one descriptor per large-array tile
 //   rs_small_sort     one workgroup per small array, every pass in LDS: count
 //                     the cells, scan them, place the keys -- the hashing and
 //                     extraction cycles of Sections 3.1 and 3.2 on chip
-//   rs_seg_histogram  per large array, every pass's cell counts in one read
-//   (the passes themselves are rs_rank_scatter<..., SEG = true>)
+//   (the large arrays' passes are rs_tile_histogram, the cell scan and
+//   rs_rank_scatter<..., kPrescannedSeg>)
 #pragma once
 
 #include "rs_kernels.h"
@@ -25,6 +26,9 @@ struct SegPlanParams {
   uint32_t *nsmall, *small_ids;
 };
 
+// One workgroup: splits the arrays into small and large ones and numbers
+// the large arrays' tiles array by array (tile_base = tiles of all earlier
+// large arrays).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void rs_seg_plan(const SegPlanParams q) {
   __shared__ uint32_t wsum[BLOCK / kWave];
@@ -60,6 +64,40 @@ __global__ __launch_bounds__(BLOCK) void rs_seg_plan(const SegPlanParams q) {
     q.tile_base[run_large] = run_tiles;
     *q.nsmall = run_small;
   }
+}
+
+struct SegTilesParams {
+  const uint64_t *seg_off;
+  const uint32_t *large_ids, *tile_base, *nlarge;
+  uint32_t tile;
+  TileDesc *tiles;   // [tiles_bound]
+  uint32_t *ntotal;  // tiles in use
+};
+
+// Resolves every large-array tile id (array by array numbering) into a
+// descriptor, one thread per id, so that the passes never search tables.
+static __global__ __launch_bounds__(256) void rs_seg_tiles(const SegTilesParams q) {
+  const uint32_t id = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t L = *q.nlarge;
+  const uint32_t total = q.tile_base[L];
+  if (id == 0) *q.ntotal = total;
+  if (id >= total) return;
+  uint32_t lo = 0, hi = L;  // last large array with tile_base <= id
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (q.tile_base[mid] <= id) lo = mid;
+    else hi = mid;
+  }
+  const uint32_t sid = q.large_ids[lo];
+  const uint64_t sb = q.seg_off[sid], se = q.seg_off[sid + 1];
+  TileDesc td;
+  td.base = sb;
+  td.len = (uint32_t)(se - sb);
+  td.j = id - q.tile_base[lo];
+  td.nt = q.tile_base[lo + 1] - q.tile_base[lo];
+  td.tb = q.tile_base[lo];
+  td.pad0 = td.pad1 = 0;
+  q.tiles[id] = td;
 }
 
 template <class Digit>
@@ -143,82 +181,6 @@ __global__ __launch_bounds__(BLOCK) void rs_small_sort(const SmallParams<Digit> 
         kout[b + e] = k[r];
         if constexpr (PAIRS) vout[b + e] = v[r];
       }
-    }
-  }
-}
-
-template <class Digit>
-struct SegHistParams {
-  Digit digit[kMaxPasses];
-  uint32_t npasses;
-  uint32_t stride;            // words per (array, pass) row
-  uint32_t tile;              // keys per tile
-  const uint64_t *seg_off;
-  const uint32_t *tile_base;  // [nlarge + 1]
-  const uint32_t *large_ids;
-  const uint32_t *nlarge;
-  uint32_t *seg_hist;         // [nlarge][npasses][stride], zero before launch
-  uint4 *zero;                // look-back words to clear
-  uint64_t zero16;
-};
-
-// Each workgroup takes a contiguous run of tiles; counts accumulate in LDS
-// while the run stays in one array and are added to that array's global
-// table when it changes, so an array costs one flush per workgroup touching
-// it rather than one per tile.
-template <typename K, class Digit, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void rs_seg_histogram(const SegHistParams<Digit> h, const K *__restrict__ keys) {
-  extern __shared__ uint32_t hist[];  // [npasses][stride]
-  __shared__ uint32_t s_row;
-  const uint32_t t = threadIdx.x;
-  const uint32_t words = h.npasses * h.stride;
-  {
-    const uint64_t per = (h.zero16 + gridDim.x - 1) / gridDim.x;
-    const uint64_t a = (uint64_t)blockIdx.x * per;
-    const uint64_t b = a + per < h.zero16 ? a + per : h.zero16;
-    const uint4 z = make_uint4(0, 0, 0, 0);
-    for (uint64_t i = a + t; i < b; i += BLOCK) h.zero[i] = z;
-  }
-  const uint32_t L = *h.nlarge;
-  const uint32_t T = h.tile_base[L];
-  const uint32_t per = (T + gridDim.x - 1) / gridDim.x;
-  const uint32_t t0 = blockIdx.x * per;
-  const uint32_t t1 = t0 + per < T ? t0 + per : T;
-  if (t0 >= t1) return;
-  for (uint32_t i = t; i < words; i += BLOCK) hist[i] = 0;
-  if (t == 0) {
-    uint32_t lo = 0, hi = L;
-    while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) / 2;
-      if (h.tile_base[mid] <= t0) lo = mid;
-      else hi = mid;
-    }
-    s_row = lo;
-  }
-  __syncthreads();
-  uint32_t row = s_row;
-  for (uint32_t tile = t0; tile < t1; ++tile) {
-    while (tile >= h.tile_base[row + 1]) ++row;  // uniform: every thread walks the same rows
-    const uint32_t sid = h.large_ids[row];
-    const uint64_t sb = h.seg_off[sid], se = h.seg_off[sid + 1];
-    const uint64_t e0 = sb + (uint64_t)(tile - h.tile_base[row]) * h.tile;
-    const uint64_t e1 = e0 + h.tile < se ? e0 + h.tile : se;
-    for (uint64_t base = e0; base < e1; base += BLOCK) {
-      const uint64_t e = base + t;
-      const bool valid = e < e1;
-      const K key = valid ? keys[e] : K{};
-      for (uint32_t p = 0; p < h.npasses; ++p) wave_count(hist + p * h.stride, valid ? h.digit[p](key) : 0u, valid);
-    }
-    const bool last_of_row = (tile + 1 == t1) || (tile + 1 >= h.tile_base[row + 1]);
-    if (last_of_row) {
-      __syncthreads();
-      uint32_t *dst = h.seg_hist + (uint64_t)row * words;
-      for (uint32_t i = t; i < words; i += BLOCK) {
-        const uint32_t c = hist[i];
-        if (c) atomicAdd(dst + i, c);
-        hist[i] = 0;
-      }
-      __syncthreads();
     }
   }
 }

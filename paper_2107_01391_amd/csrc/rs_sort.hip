@@ -1,12 +1,17 @@
 // rs_sort.hip -- C ABI and launch sequences of the single-array sort.
 //
-// rs_sort_pairs / rs_sort_keys (grouped passes):
-//   1. rs_fill                 clear the control words
-//   2. rs_digit_hash_histogram one read of the keys: every pass's cell counts
-//                              (per-workgroup tables), clears look-back words
+// rs_sort_pairs / rs_sort_keys, chained passes (small arrays):
+//   1. rs_fill                 clear the control words and count tables
+//   2. rs_digit_hash_histogram one read of the keys: every pass's cell counts,
+//                              clears the look-back words on the way
 //   3. rs_cell_scan            exclusive scan of every pass's counts
 //   4. rs_rank_scatter x P     stable passes, least significant group first,
 //                              ping-ponging between the output and scratch
+// prescanned passes (large arrays), per pass (rs_passes.h):
+//   1. rs_tile_histogram       per-tile counts of the pass's group
+//   2. rs_cell_scan_reduce/_spine/_down   one exclusive scan of that table,
+//                              cell-major: every tile's output offset per cell
+//   3. rs_rank_scatter         stable scatter, offsets read from the table
 // rs_sort_keys on a small space (literal):
 //   1. rs_fill                 clear the cell counts
 //   2. rs_cell_count           S[cell]++ over the whole space
@@ -21,6 +26,7 @@
 
 #include "rs_internal.h"
 #include "rs_kernels.h"
+#include "rs_passes.h"
 
 namespace rs {
 
@@ -68,7 +74,7 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
                             const uint32_t *vals_in, uint32_t *vals_out, void *tmp, hipStream_t stream) {
   char *base = (char *)tmp;
   uint32_t *ctrl = (uint32_t *)(base + pl.off_ctrl);
-  uint32_t *partials = (uint32_t *)(base + pl.off_partials);
+  uint32_t *counts = ctrl + pl.npasses + 1 + pl.scan_chunks;  // [P][bins]
   uint32_t *dstart = (uint32_t *)(base + pl.off_dstart);
   uint32_t *status = (uint32_t *)(base + pl.off_status);
   rs_status st = launch_fill(ctrl, pl.ctrl_bytes, 0, stream);
@@ -80,24 +86,21 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   for (uint32_t i = 0; i < pl.npasses; ++i) h.digit[i] = digits[i];
   h.npasses = pl.npasses;
   h.stride = pl.bins;
+  h.copies = pl.hist_copies;
   h.n = pl.n;
-  h.partials = partials;
+  h.counts = counts;
   h.zero = (uint4 *)status;
   h.zero16 = pl.status_bytes / 16;
-  const size_t lds = (size_t)pl.npasses * pl.bins * 4;
-  if (((uintptr_t)keys_in % 16) == 0) {
-    RS_TIMED("rs_digit_hash_histogram", stream, hipLaunchKernelGGL((rs_digit_hash_histogram<K, Digit, 256>), dim3(pl.hist_grid), dim3(256), lds, stream, h,
-                       (const K *)keys_in));
-  } else {
-    return fail(RS_ERR_UNSUPPORTED, "keys_in must be 16-byte aligned");
-  }
+  const size_t lds = (size_t)pl.hist_copies * (pl.npasses * pl.bins + 1) * 4;
+  if (((uintptr_t)keys_in % 16) != 0) return fail(RS_ERR_UNSUPPORTED, "keys_in must be 16-byte aligned");
+  RS_TIMED("rs_digit_hash_histogram", stream,
+           hipLaunchKernelGGL((rs_digit_hash_histogram<K, Digit, 256>), dim3(pl.hist_grid), dim3(256), lds, stream,
+                              h, (const K *)keys_in));
   if ((st = check_launch("rs_digit_hash_histogram")) != RS_OK) return st;
 
   // 3. exclusive scan of each pass's cells
   ScanParams s;
-  s.in = partials;
-  s.part_stride = (uint64_t)pl.npasses * pl.bins;
-  s.nparts = pl.hist_grid;
+  s.in = counts;
   s.nseg = pl.npasses;
   s.cells = pl.bins;
   s.stride = pl.bins;
@@ -107,8 +110,9 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   s.chunks_per_seg = (pl.bins + kScanChunk - 1) / kScanChunk;
   s.nseg_dev = nullptr;
   s.nseg_mul = 1;
-  RS_TIMED("rs_cell_scan", stream, hipLaunchKernelGGL((rs_cell_scan<kScanBlock, kScanItems>), dim3(s.nseg * s.chunks_per_seg), dim3(kScanBlock), 0,
-                     stream, s));
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan<kScanBlock, kScanItems>), dim3(s.nseg * s.chunks_per_seg),
+                              dim3(kScanBlock), 0, stream, s));
   if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
 
   // 4. stable passes; buffer X = output, Y = scratch; pass P-1 writes X
@@ -143,14 +147,19 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
     pp.digit_start = dstart + (size_t)i * pl.bins;
     pp.status = status + (size_t)i * pl.ntiles * pl.bins;
     pp.tile_counter = ctrl + i;
-    const dim3 grid((uint32_t)pl.ntiles), blk(256);
+    pp.ntiles = (uint32_t)pl.ntiles;
+    const dim3 blk(256);
     constexpr int KPT = sizeof(K) >= 16 ? 8 : 16;  // LDS staging of one tile: 32 KiB at most
-    if (pl.pairs)
-      RS_TIMED("rs_rank_scatter", stream, hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, true, false>), grid, blk, 0, stream, pp, src, dst,
-                         srcv, dstv));
-    else
-      RS_TIMED("rs_rank_scatter", stream, hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, false, false>), grid, blk, 0, stream, pp, src,
-                         dst, nullptr, nullptr));
+    if (pl.pairs) {
+      auto kern = rs_rank_scatter<K, Digit, BITS, 256, KPT, true, kChained>;
+      const dim3 grid((uint32_t)pl.ntiles);
+      RS_TIMED("rs_rank_scatter", stream, hipLaunchKernelGGL(kern, grid, blk, 0, stream, pp, src, dst, srcv, dstv));
+    } else {
+      auto kern = rs_rank_scatter<K, Digit, BITS, 256, KPT, false, kChained>;
+      const dim3 grid((uint32_t)pl.ntiles);
+      RS_TIMED("rs_rank_scatter", stream,
+               hipLaunchKernelGGL(kern, grid, blk, 0, stream, pp, src, dst, nullptr, nullptr));
+    }
     if ((st = check_launch("rs_rank_scatter")) != RS_OK) return st;
     src = dst;
     srcv = dstv;
@@ -158,20 +167,38 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   return RS_OK;
 }
 
+template <typename K, class Digit, int BITS>
+static rs_status run_prescanned(const Plan &pl, const Digit *digits, const void *keys_in, void *keys_out,
+                                const uint32_t *vals_in, uint32_t *vals_out, void *tmp, hipStream_t stream) {
+  char *base = (char *)tmp;
+  if (((uintptr_t)keys_in % 16) != 0) return fail(RS_ERR_UNSUPPORTED, "keys_in must be 16-byte aligned");
+  return prescanned_passes<K, Digit, BITS, false>(
+      pl, digits, pl.npasses, keys_in, keys_out, vals_in, vals_out, base + pl.off_keys_alt,
+      pl.pairs ? (uint32_t *)(base + pl.off_vals_alt) : nullptr, pl.n, pl.ntiles, (uint32_t *)(base + pl.off_table),
+      (uint32_t *)(base + pl.off_sums), nullptr, nullptr, stream);
+}
+
+template <typename K, class Digit, int BITS>
+static rs_status run_single(const Plan &pl, const Digit *digits, const void *ki, void *ko, const uint32_t *vi,
+                            uint32_t *vo, void *tmp, hipStream_t s) {
+  if (pl.prescanned) return run_prescanned<K, Digit, BITS>(pl, digits, ki, ko, vi, vo, tmp, s);
+  return run_passes<K, Digit, BITS>(pl, digits, ki, ko, vi, vo, tmp, s);
+}
+
 template <typename K, class Digit>
 static rs_status run_bits(const Plan &pl, const Digit *digits, const void *ki, void *ko, const uint32_t *vi,
                           uint32_t *vo, void *tmp, hipStream_t s) {
   if constexpr (sizeof(K) >= 16) {  // strings: 27^2 = 729 cells per pass
     if (pl.bits != 10) return fail(RS_ERR_UNSUPPORTED, "string passes use 10-bit cells");
-    return run_passes<K, Digit, 10>(pl, digits, ki, ko, vi, vo, tmp, s);
+    return run_single<K, Digit, 10>(pl, digits, ki, ko, vi, vo, tmp, s);
   }
   switch (pl.bits) {
   case 8:
-    return run_passes<K, Digit, 8>(pl, digits, ki, ko, vi, vo, tmp, s);
+    return run_single<K, Digit, 8>(pl, digits, ki, ko, vi, vo, tmp, s);
   case 10:
-    return run_passes<K, Digit, 10>(pl, digits, ki, ko, vi, vo, tmp, s);
+    return run_single<K, Digit, 10>(pl, digits, ki, ko, vi, vo, tmp, s);
   default:
-    return run_passes<K, Digit, 11>(pl, digits, ki, ko, vi, vo, tmp, s);
+    return run_single<K, Digit, 11>(pl, digits, ki, ko, vi, vo, tmp, s);
   }
 }
 
@@ -194,8 +221,6 @@ static rs_status run_literal(const Plan &pl, const void *keys_in, void *keys_out
   if ((st = check_launch("rs_cell_count")) != RS_OK) return st;
   ScanParams s;
   s.in = counts;
-  s.part_stride = 0;
-  s.nparts = 1;
   s.nseg = 1;
   s.cells = pl.literal_cells;
   s.stride = pl.literal_cells;

@@ -160,3 +160,100 @@ def test_validate_rejects_out_of_space_keys():
     ok_keys = np.array([5, 999_999, 3], np.uint32)
     gk, _ = gpu_sort(ok_keys, None, "u32", 10, 6, validate=True)
     assert gk.tolist() == [3, 5, 999_999]
+
+
+# ------------------------------------------------------- prescanned passes
+# Large single arrays run every pass as per-tile counts, one flat scan and a
+# scatter whose offsets come from the scanned table; small ones chain their
+# tiles by look-back.  The switch point is lowered here so that ragged,
+# skewed and in-place cases stay small; setting it above n forces the chain.
+
+@pytest.fixture()
+def prescanned(monkeypatch):
+    monkeypatch.setenv("RS_PRESCAN_MIN_N", "1")
+    yield
+
+
+@pytest.fixture()
+def chained(monkeypatch):
+    monkeypatch.setenv("RS_PRESCAN_MIN_N", str(1 << 40))
+    yield
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, TILE_U32 - 1, TILE_U32, TILE_U32 + 1, 8 * TILE_U32 + 1, 70_001, 1 << 20])
+def test_prescanned_u32_pairs(prescanned, n):
+    _say(f"prescanned u32 pairs n={n}")
+    w = workloads.uniform_u32_pairs(n)
+    gk, gv = gpu_sort(w.keys, w.vals, "u32", 256, 4)
+    ok, ov = oracle_sort(w.keys, w.vals, "u32", 256, 4)
+    assert_same(gk, gv, ok, ov, f"n={n}")
+
+
+def test_chained_large(chained):
+    _say("chained u32 pairs n=3M")
+    w = workloads.uniform_u32_pairs(3_000_017)
+    gk, gv = gpu_sort(w.keys, w.vals, "u32", 256, 4)
+    ok, ov = oracle_sort(w.keys, w.vals, "u32", 256, 4)
+    assert_same(gk, gv, ok, ov)
+
+
+def test_prescanned_keys_only_and_in_place(prescanned):
+    _say("prescanned keys only, in place")
+    w = workloads.uniform_u32_pairs(99_999)
+    gk, _ = gpu_sort(w.keys, None, "u32", 256, 4)
+    ok, _ = oracle_sort(w.keys, None, "u32", 256, 4)
+    assert_same(gk, None, ok, None)
+    gk, gv = gpu_sort(w.keys, w.vals, "u32", 256, 4, in_place=True)
+    ok, ov = oracle_sort(w.keys, w.vals, "u32", 256, 4)
+    assert_same(gk, gv, ok, ov)
+
+
+def test_prescanned_fixed_point_skewed(prescanned):
+    """Fixed point: 1000-cell groups, most keys in a few cells (the lognormal
+    skew), three passes: odd, so in place starts from a copy."""
+    _say("prescanned fixed point")
+    w = workloads.fixed_point_decimals(300_007)
+    gk, gv = gpu_sort(w.keys, w.vals, "fixed_i64", 10, 9, frac_digits=3)
+    ok, ov = oracle_sort(w.keys, w.vals, "fixed_i64", 10, 9)
+    assert_same(gk, gv, ok, ov)
+    gk, gv = gpu_sort(w.keys, w.vals, "fixed_i64", 10, 9, in_place=True)
+    assert_same(gk, gv, ok, ov, "in place, odd pass count")
+
+
+def test_prescanned_strings_and_u64(prescanned):
+    _say("prescanned strings")
+    w = workloads.strings16(60_001)
+    gk, gv = gpu_sort(w.keys, w.vals, "str", 27, 16)
+    ok, ov = oracle_sort(w.keys, w.vals, "str", 27, 16)
+    assert_same(gk, gv, ok, ov)
+    _say("prescanned u64")
+    rng = np.random.default_rng(3)
+    keys = rng.integers(0, 2**64, 50_001, dtype=np.uint64)
+    vals = np.arange(keys.shape[0], dtype=np.uint32)
+    gk, gv = gpu_sort(keys, vals, "u64", 256, 8)
+    ok, ov = oracle_sort(keys, vals, "u64", 256, 8)
+    assert_same(gk, gv, ok, ov)
+
+
+@pytest.mark.parametrize("distinct", [1, 5])
+def test_prescanned_hot_cells(prescanned, distinct):
+    _say(f"prescanned skewed distinct={distinct}")
+    rng = np.random.default_rng(100 + distinct)
+    pool = rng.integers(0, 2**32, distinct, dtype=np.uint32)
+    keys = pool[rng.integers(0, distinct, 200_003)]
+    vals = np.arange(keys.shape[0], dtype=np.uint32)
+    gk, gv = gpu_sort(keys, vals, "u32", 256, 4)
+    ok, ov = oracle_sort(keys, vals, "u32", 256, 4)
+    assert_same(gk, gv, ok, ov)
+
+
+@pytest.mark.parametrize("base,ndims,bits", [(16, 8, 4), (2, 32, 11), (4, 16, 10)])
+def test_prescanned_digit_widths(prescanned, monkeypatch, base, ndims, bits):
+    """Other pass widths on power-of-two bases: 8 passes of 16 cells; passes
+    of 2048, 2048 and 1024 cells; 1024-cell passes."""
+    monkeypatch.setenv("RS_DIGIT_BITS", str(bits))
+    _say(f"prescanned base {base} digit bits {bits}")
+    w = workloads.uniform_u32_pairs(123_457)
+    gk, gv = gpu_sort(w.keys, w.vals, "u32", base, ndims)
+    ok, ov = oracle_sort(w.keys, w.vals, "u32", base, ndims)
+    assert_same(gk, gv, ok, ov)
