@@ -3,15 +3,16 @@
 
 Default workload: 268,435,456 uint32 keys uniform over [0, 2^32) with a
 uint32 index payload, base-256 digits (4 dimensions), stable ascending sort
-through rs_sort_pairs.  One step = one whole sort (histogram, scans and the
-four stable passes) with inputs already resident in HBM.
+through rs_sort_pairs.  One step = one whole sort (per pass: per-tile
+counts, scan, stable scatter) with inputs already resident in HBM.
 
 Prints one JSON line: the whole-sort rate in Gkeys/s, the dominant kernel's
 (rs_rank_scatter) achieved bandwidth against the 8 TB/s HBM peak, measured
-live with HIP events on the launch stream over the timed steps, and the CPU
-oracle timed on a bounded sample on this host.
+live with HIP events on the launch stream over the timed steps, the CPU
+oracle timed on a bounded sample on this host, and the batched form against
+one call per array on 4096 arrays of log-uniform size in [2^10, 2^22].
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-batched]
 """
 from __future__ import annotations
 
@@ -78,16 +79,114 @@ def check_sorted(torch, keys_in, keys_out, vals_out, n):
     return ok
 
 
+def batched_vs_per_array(torch, B, workloads, count: int) -> dict:
+    """`count` arrays with log-uniform sizes in [2^10, 2^22] (the seeded size
+    law), uniform u32 keys and local-index payloads drawn on the device.
+    Per-array: one rs_sort_pairs call per array, on 1 and on 4 streams (the
+    better is kept); an array's latency runs from the common start to the
+    event after its own sort.  Batched: one rs_sort_batched sequence, in
+    which every array completes at the makespan."""
+    from paper_2107_01391_amd import api
+    sizes = workloads.batched_sizes(count)
+    offsets = np.zeros(count + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(sizes)
+    total = int(offsets[-1])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(workloads.SEED_BASE + 4)
+    keys = torch.randint(0, 2**32, (total,), dtype=torch.int64, device="cuda", generator=g).to(torch.int32)
+    starts = torch.repeat_interleave(torch.from_numpy(offsets[:-1].astype(np.int64)).cuda(),
+                                     torch.from_numpy(sizes).cuda())
+    vals = (torch.arange(total, dtype=torch.int64, device="cuda") - starts).to(torch.int32)
+    del starts
+    keys_out, vals_out = torch.empty_like(keys), torch.empty_like(vals)
+    desc = B.key_desc("u32", base=256, ndims=4)
+    off_dev = api.to_device(offsets)
+    res = {"arrays": count, "total_pairs": total, "size_law": "log-uniform [2^10, 2^22], seeded",
+           "keys": "uniform u32 drawn on the device (torch Philox, seeded); local-index payload"}
+
+    def run(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            r = fn()
+            if best is None or r["makespan_ms"] < best["makespan_ms"]:
+                best = r
+        return best
+
+    # batched: one sequence for every array
+    tmp = torch.empty(B.rs_batched_temp_bytes(desc, total, count, True), dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream()
+
+    def batched_once():
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        B.rs_sort_batched(desc, keys, keys_out, vals, vals_out, off_dev, count, total, tmp, tmp.numel(), st)
+        b.record(st)
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        return {"makespan_ms": round(ms, 3), "p50_ms": round(ms, 3), "p99_ms": round(ms, 3)}
+
+    res["batched"] = run(batched_once)
+    # spot check: three arrays sorted with ties in input order
+    for i in (0, count // 2, count - 1):
+        lo, hi = int(offsets[i]), int(offsets[i + 1])
+        k = keys_out[lo:hi].to(torch.int64) & 0xFFFFFFFF
+        v = vals_out[lo:hi].to(torch.int64)
+        src = keys[lo:hi].to(torch.int64) & 0xFFFFFFFF
+        good = bool((k[1:] >= k[:-1]).all()) and bool((src[v] == k).all())
+        good = good and bool(((k[1:] != k[:-1]) | (v[1:] > v[:-1])).all())
+        res.setdefault("spot_check", True)
+        res["spot_check"] = res["spot_check"] and good
+    del tmp
+
+    per = []
+    for nstreams in (1, 4):
+        streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        tmps = [torch.empty(B.rs_temp_bytes(desc, int(sizes.max()), True), dtype=torch.uint8, device="cuda")
+                for _ in range(nstreams)]
+
+        def per_array_once():
+            start = torch.cuda.Event(enable_timing=True)
+            start.record(st)
+            for s in streams:
+                s.wait_event(start)
+            done = []
+            for i in range(count):
+                s = streams[i % nstreams]
+                lo, hi = int(offsets[i]), int(offsets[i + 1])
+                B.rs_sort_pairs(desc, keys[lo:], keys_out[lo:], vals[lo:], vals_out[lo:], hi - lo,
+                                tmps[i % nstreams], tmps[i % nstreams].numel(), s)
+                e = torch.cuda.Event(enable_timing=True)
+                e.record(s)
+                done.append(e)
+            torch.cuda.synchronize()
+            lat = np.array([start.elapsed_time(e) for e in done])
+            return {"makespan_ms": round(float(lat.max()), 3), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 3), "streams": nstreams}
+
+        per.append(run(per_array_once))
+        del tmps
+    res["per_array"] = min(per, key=lambda r: r["makespan_ms"])
+    res["per_array_all"] = per
+    for k in ("batched", "per_array"):
+        res[k]["gkeys_per_s"] = round(total / (res[k]["makespan_ms"] / 1e3) / 1e9, 3)
+    res["batched_speedup"] = round(res["per_array"]["makespan_ms"] / res["batched"]["makespan_ms"], 3)
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=FULL_N)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 26)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-arrays", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one plain 1 GiB device copy (scale reference for PMC byte counters)")
+                    help="also run a plain 1 GiB read + 1 GiB write kernel (scale reference for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sort runs on a single MI355X; a run on more GPUs is not part "
@@ -112,10 +211,13 @@ def main() -> int:
     stream = torch.cuda.current_stream()
 
     if args.copy_calibration:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        # a plain streaming kernel of known size for the PMC byte counters:
+        # reads 1 GiB and writes 1 GiB (torch's elementwise bitwise_not)
+        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
-        a.fill_(1)
-        b.copy_(a)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            torch.bitwise_not(a, out=b)
         torch.cuda.synchronize()
         del a, b
 
@@ -131,16 +233,21 @@ def main() -> int:
 
     B.rs_prof_enable(True)
     torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record(stream)
     for _ in range(args.steps):
         step()
+    ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches, total_ms = B.rs_prof_query("rs_rank_scatter")
-    hist_launches, hist_ms = B.rs_prof_query("rs_digit_hash_histogram")
+    kernel_ms = {k: round(B.rs_prof_query(k)[1] / args.steps, 4)
+                 for k in ("rs_tile_histogram", "rs_cell_scan", "rs_rank_scatter", "rs_digit_hash_histogram")}
     B.rs_prof_enable(False)
 
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    wall_ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_per_step / 1e3) / 1e9
     avg_ms = total_ms / max(launches, 1)
     per_launch_bytes = n * 16  # read key + value, write key + value (4 B each)
@@ -150,10 +257,20 @@ def main() -> int:
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "rs_rank_scatter", "launches": launches, "avg_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": per_launch_bytes}
-    whole = {"algorithmic_bytes_per_pair": 20, "planned_bytes_per_pair": 68,
+    passes = launches // max(args.steps, 1)
+    planned = passes * 20  # per pass: count read 4 B, scatter read 8 B and write 8 B
+    whole = {"algorithmic_bytes_per_pair": 20, "planned_bytes_per_pair": planned, "passes": passes,
              "algorithmic_GBps": round(20 * n / (ms_per_step / 1e3) / 1e9, 1),
-             "planned_GBps": round(68 * n / (ms_per_step / 1e3) / 1e9, 1),
-             "histogram_avg_ms": round(hist_ms / max(hist_launches, 1), 4)}
+             "planned_GBps": round(planned * n / (ms_per_step / 1e3) / 1e9, 1),
+             "planned_frac_of_peak": round(planned * n / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+             "wall_ms_per_step": round(wall_ms_per_step, 4), "kernel_ms_per_step": kernel_ms}
+    del keys_out, vals_out, tmp
+    torch.cuda.empty_cache()
+
+    batched = None
+    if not args.no_batched:
+        print("[bench] batched vs per-array", file=sys.stderr, flush=True)
+        batched = batched_vs_per_array(torch, B, workloads, args.batched_arrays)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -167,8 +284,9 @@ def main() -> int:
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"uniform_u32_pairs: {n} uint32 keys uniform over [0, 2^32), uint32 index payload, "
                                "base 256, 4 dimensions, stable ascending (rs_sort_pairs)",
-                   "n": n, "passes": 4, "tile_keys": 4096},
-        "roofline": roofline, "whole_sort": whole, "cpu_baseline": cpu, "output_check": ok,
+                   "n": n, "passes": passes, "tile_keys": 4096},
+        "roofline": roofline, "whole_sort": whole, "cpu_baseline": cpu, "batched_vs_per_array": batched,
+        "output_check": ok,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)

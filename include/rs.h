@@ -21,6 +21,10 @@
  *     from hipMalloc or a framework allocator on the current device).  The
  *     caller owns every buffer; the library allocates and frees nothing in
  *     the sort calls and keeps no pointer after the stream work completes.
+ *   - Keys are aligned to their size (4 bytes for u32, 8 for u64 and fixed
+ *     point, 16 for 16-byte strings), values to 4 bytes and tmp to 256
+ *     bytes; anything else returns RS_ERR_UNSUPPORTED.  Arrays may start at
+ *     any such element offset (slices of a larger buffer).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls are asynchronous: they enqueue kernels and return.  Errors found
  *     before launching are returned; faults during execution surface at the

@@ -75,7 +75,8 @@ rs_status rs_sort_batched(const rs_key_desc *desc, const void *keys_in, void *ke
   if (st != RS_OK) return fail(st, why);
   if (tmp_bytes < p.total)
     return fail(RS_ERR_TMP_TOO_SMALL, "tmp_bytes " + std::to_string(tmp_bytes) + " < " + std::to_string(p.total));
-  if ((uintptr_t)tmp % 256 != 0) return fail(RS_ERR_UNSUPPORTED, "tmp must be 256-byte aligned");
+  if ((st = check_alignment(p.key, keys_in, keys_out, vals_in, vals_out, tmp)) != RS_OK) return st;
+  if ((uintptr_t)d_seg_offsets % 8) return fail(RS_ERR_UNSUPPORTED, "d_seg_offsets must be 8-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   if (desc->flags & RS_FLAG_VALIDATE) {
     st = validate_keys(p, keys_in, total, tmp, s);

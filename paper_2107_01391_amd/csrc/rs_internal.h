@@ -14,6 +14,9 @@ extern thread_local std::string g_last_error;
 rs_status fail(rs_status st, const std::string &why);
 int cu_count();
 rs_status check_launch(const char *what);
+// Keys aligned to their size, values to 4 bytes, tmp to 256 (null passes).
+rs_status check_alignment(const KeyInfo &k, const void *ki, const void *ko, const void *vi, const void *vo,
+                          const void *tmp);
 rs_status launch_fill(void *p, size_t bytes, uint32_t value, hipStream_t stream);
 rs_status validate_keys(const Plan &pl, const void *keys, uint64_t n, void *tmp, hipStream_t s);
 rs_status run_plan(const Plan &pl, const void *ki, void *ko, const uint32_t *vi, uint32_t *vo, void *tmp,

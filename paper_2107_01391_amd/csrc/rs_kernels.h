@@ -40,11 +40,12 @@ static __global__ void rs_fill(uint4 *__restrict__ p, uint64_t n16, uint32_t val
 }
 
 // Loads VEC consecutive keys of this thread with one 128-bit load when the
-// whole group is in range (keys are 16-byte aligned), else one by one.
+// whole group is in range and the array is 16-byte aligned (`aligned`, the
+// same for every thread of a launch), else one by one.
 template <typename K, int VEC>
-__device__ __forceinline__ void load_keys(const K *__restrict__ keys, uint64_t e, uint64_t end, K (&k)[VEC],
-                                          bool (&valid)[VEC]) {
-  if (e + VEC <= end) {
+__device__ __forceinline__ void load_keys(const K *__restrict__ keys, bool aligned, uint64_t e, uint64_t end,
+                                          K (&k)[VEC], bool (&valid)[VEC]) {
+  if (aligned && e + VEC <= end) {
     const uint4 raw = *reinterpret_cast<const uint4 *>(keys + e);
     const K *kk = reinterpret_cast<const K *>(&raw);
 #pragma unroll
@@ -97,6 +98,7 @@ __global__ __launch_bounds__(BLOCK) void rs_digit_hash_histogram(const HistParam
 
   constexpr int UNROLL = 4;  // loads in flight per thread before counting
   constexpr uint64_t kStep = (uint64_t)BLOCK * VEC;
+  const bool aligned = ((uintptr_t)keys % 16) == 0;
   const uint64_t per = ((h.n + gridDim.x - 1) / gridDim.x + kStep * UNROLL - 1) / (kStep * UNROLL) * (kStep * UNROLL);
   const uint64_t a = (uint64_t)blockIdx.x * per;
   const uint64_t b = a + per < h.n ? a + per : h.n;
@@ -104,7 +106,8 @@ __global__ __launch_bounds__(BLOCK) void rs_digit_hash_histogram(const HistParam
     K k[UNROLL][VEC];
     bool valid[UNROLL][VEC];
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) load_keys<K, VEC>(keys, base + u * kStep + (uint64_t)t * VEC, b, k[u], valid[u]);
+    for (int u = 0; u < UNROLL; ++u)
+      load_keys<K, VEC>(keys, aligned, base + u * kStep + (uint64_t)t * VEC, b, k[u], valid[u]);
     for (uint32_t p = 0; p < h.npasses; ++p) {
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u)
@@ -204,14 +207,16 @@ __global__ __launch_bounds__(BLOCK) void rs_tile_histogram(const TileHistParams<
     uint32_t *row = cnt + jj * tstride;
     if constexpr (!SEG) {
       // one array: tiles start at multiples of TILE, so 128-bit loads line up
+      // when the array does
       constexpr int VEC = 16 / sizeof(K);
+      const bool aligned = ((uintptr_t)keys % 16) == 0;
       constexpr int UNROLL = TILE / (BLOCK * VEC) < 4 ? TILE / (BLOCK * VEC) : 4;
       for (uint64_t base = sp.elem0; base < sp.end; base += (uint64_t)BLOCK * VEC * UNROLL) {
         K k[UNROLL][VEC];
         bool valid[UNROLL][VEC];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
-          load_keys<K, VEC>(keys, base + (uint64_t)(u * BLOCK + t) * VEC, sp.end, k[u], valid[u]);
+          load_keys<K, VEC>(keys, aligned, base + (uint64_t)(u * BLOCK + t) * VEC, sp.end, k[u], valid[u]);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll

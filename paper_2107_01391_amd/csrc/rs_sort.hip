@@ -92,7 +92,6 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   h.zero = (uint4 *)status;
   h.zero16 = pl.status_bytes / 16;
   const size_t lds = (size_t)pl.hist_copies * (pl.npasses * pl.bins + 1) * 4;
-  if (((uintptr_t)keys_in % 16) != 0) return fail(RS_ERR_UNSUPPORTED, "keys_in must be 16-byte aligned");
   RS_TIMED("rs_digit_hash_histogram", stream,
            hipLaunchKernelGGL((rs_digit_hash_histogram<K, Digit, 256>), dim3(pl.hist_grid), dim3(256), lds, stream,
                               h, (const K *)keys_in));
@@ -171,7 +170,6 @@ template <typename K, class Digit, int BITS>
 static rs_status run_prescanned(const Plan &pl, const Digit *digits, const void *keys_in, void *keys_out,
                                 const uint32_t *vals_in, uint32_t *vals_out, void *tmp, hipStream_t stream) {
   char *base = (char *)tmp;
-  if (((uintptr_t)keys_in % 16) != 0) return fail(RS_ERR_UNSUPPORTED, "keys_in must be 16-byte aligned");
   return prescanned_passes<K, Digit, BITS, false>(
       pl, digits, pl.npasses, keys_in, keys_out, vals_in, vals_out, base + pl.off_keys_alt,
       pl.pairs ? (uint32_t *)(base + pl.off_vals_alt) : nullptr, pl.n, pl.ntiles, (uint32_t *)(base + pl.off_table),
@@ -293,6 +291,16 @@ rs_status validate_keys(const Plan &pl, const void *keys, uint64_t n, void *tmp,
   return RS_OK;
 }
 
+rs_status check_alignment(const KeyInfo &k, const void *ki, const void *ko, const void *vi, const void *vo,
+                          const void *tmp) {
+  const uintptr_t kb = k.key_bytes;
+  if ((uintptr_t)ki % kb || (uintptr_t)ko % kb)
+    return fail(RS_ERR_UNSUPPORTED, "keys must be aligned to the key size (" + std::to_string(kb) + " bytes)");
+  if ((uintptr_t)vi % 4 || (uintptr_t)vo % 4) return fail(RS_ERR_UNSUPPORTED, "values must be 4-byte aligned");
+  if ((uintptr_t)tmp % 256) return fail(RS_ERR_UNSUPPORTED, "tmp must be 256-byte aligned");
+  return RS_OK;
+}
+
 rs_status run_plan(const Plan &pl, const void *ki, void *ko, const uint32_t *vi, uint32_t *vo, void *tmp,
                    hipStream_t s) {
   if (pl.n == 0) return RS_OK;
@@ -361,7 +369,7 @@ static rs_status sort_common(const rs_key_desc *desc, const void *keys_in, void 
   if (st != RS_OK) return fail(st, why);
   if (tmp_bytes < pl.total)
     return fail(RS_ERR_TMP_TOO_SMALL, "tmp_bytes " + std::to_string(tmp_bytes) + " < " + std::to_string(pl.total));
-  if ((uintptr_t)tmp % 256 != 0) return fail(RS_ERR_UNSUPPORTED, "tmp must be 256-byte aligned");
+  if ((st = check_alignment(pl.key, keys_in, keys_out, vals_in, vals_out, tmp)) != RS_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   if (desc->flags & RS_FLAG_VALIDATE) {
     st = validate_keys(pl, keys_in, n, tmp, s);

@@ -139,6 +139,37 @@ def test_in_place(kind, base, ndims):
     assert_same(gk, gv, ok, ov)
 
 
+@pytest.mark.parametrize("prescan", [False, True])
+@pytest.mark.parametrize("kind,base,ndims,elem", [("u32", 256, 4, 1), ("u32", 256, 4, 3), ("u64", 256, 8, 1)])
+def test_slices_not_16_byte_aligned(monkeypatch, prescan, kind, base, ndims, elem):
+    """Arrays that start `elem` keys into a buffer: the 128-bit count loads
+    give way to one key per load."""
+    import torch
+    monkeypatch.setenv("RS_PRESCAN_MIN_N", "1" if prescan else str(1 << 40))
+    _say(f"slice at +{elem} {kind} prescan={prescan}")
+    n = 3 * TILE_U32 + 77
+    rng = np.random.default_rng(5 + elem)
+    dt = np.uint32 if kind == "u32" else np.uint64
+    keys = rng.integers(0, np.iinfo(dt).max, n, dtype=dt, endpoint=True)
+    vals = np.arange(n, dtype=np.uint32)
+    kb = keys.itemsize
+    kbuf = torch.zeros((n + elem) * kb, dtype=torch.uint8, device="cuda")
+    kbuf[elem * kb:].copy_(torch.from_numpy(keys.view(np.uint8)).cuda())
+    vbuf = torch.zeros((n + 1) * 4, dtype=torch.uint8, device="cuda")
+    vbuf[4:].copy_(torch.from_numpy(vals.view(np.uint8)).cuda())
+    kout = torch.zeros((n + elem) * kb, dtype=torch.uint8, device="cuda")
+    vout = torch.zeros((n + 1) * 4, dtype=torch.uint8, device="cuda")
+    d = B.key_desc(kind, base=base, ndims=ndims)
+    tmp = torch.empty(B.rs_temp_bytes(d, n, True), dtype=torch.uint8, device="cuda")
+    B.rs_sort_pairs(d, kbuf[elem * kb:], kout[elem * kb:], vbuf[4:], vout[4:], n, tmp, tmp.numel())
+    torch.cuda.synchronize()
+    gk = kout[elem * kb:].cpu().numpy().view(dt)
+    gv = vout[4:].cpu().numpy().view(np.uint32)
+    ok, ov = oracle_sort(keys, vals, kind, base, ndims)
+    assert_same(gk, gv, ok, ov)
+    assert not kout[: elem * kb].any() and not vout[:4].any(), "wrote before the slice"
+
+
 def test_deterministic_repeat():
     _say("determinism")
     w = workloads.uniform_u32_pairs(500_000)

@@ -92,6 +92,26 @@ def test_null_and_small_tmp_rejected_before_launch():
     assert lib.rs_sort_pairs(None, fake, fake, fake, fake, 1000, fake, need, None) == 1
 
 
+@pytest.mark.parametrize("kind,kptr,vptr,tptr", [
+    ("u32", 258, 512, 1024),   # keys off their 4-byte size
+    ("u64", 260, 512, 1024),   # keys off their 8-byte size
+    ("str", 264, 512, 1024),   # 16-byte rows off 16 bytes
+    ("u32", 256, 514, 1024),   # values off 4 bytes
+    ("u32", 256, 512, 1028),   # tmp off 256 bytes
+])
+def test_misaligned_pointers_rejected_before_launch(kind, kptr, vptr, tptr):
+    """Pointers are never dereferenced: the alignment check fails first."""
+    d = B.key_desc(kind)
+    lib = B.load_library()
+    need = B.rs_temp_bytes(d, 1000, True)
+    k, v, t = (ctypes.c_void_p(x) for x in (kptr, vptr, tptr))
+    assert lib.rs_sort_pairs(ctypes.byref(d), k, k, v, v, 1000, t, need, None) == 5
+    assert "align" in B.rs_last_error()
+    offs = ctypes.c_void_p(2048)
+    need_b = B.rs_batched_temp_bytes(d, 1000, 4, True)
+    assert lib.rs_sort_batched(ctypes.byref(d), k, k, v, v, offs, 4, 1000, t, need_b, None) == 5
+
+
 def test_codec_host_build(tmp_path):
     """The digit codecs, built for the host from the same header the kernels
     use, against plain division / byte arithmetic on edge and random values."""
