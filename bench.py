@@ -284,7 +284,7 @@ def main() -> int:
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": f"uniform_u32_pairs: {n} uint32 keys uniform over [0, 2^32), uint32 index payload, "
                                "base 256, 4 dimensions, stable ascending (rs_sort_pairs)",
-                   "n": n, "passes": passes, "tile_keys": 4096},
+                   "n": n, "passes": passes},
         "roofline": roofline, "whole_sort": whole, "cpu_baseline": cpu, "batched_vs_per_array": batched,
         "output_check": ok,
         "device": torch.cuda.get_device_name(0),

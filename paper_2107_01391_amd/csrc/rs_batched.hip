@@ -10,12 +10,13 @@ namespace rs {
 // form sorts every group of every array (least significant first).
 static rs_status make_batched(const rs_key_desc *desc, uint64_t total, uint32_t nseg, bool pairs, Plan *p,
                               std::string *why) {
-  rs_status st = make_plan(desc, 1, true, current_tuning(desc, total, pairs), p, why);
+  const Tuning tune = current_tuning(desc, total, pairs);
+  rs_status st = make_plan(desc, 1, true, tune, p, why);
   if (st != RS_OK) return st;
   p->pairs = pairs;
   p->literal = false;
   p->prescanned = false;
-  st = make_seg_layout(*p, p->npasses, total, nseg, true, &p->seg, why);
+  st = make_seg_layout(*p, p->npasses, total, nseg, true, prescan_block(tune, p->key.key_bytes, p->bits), &p->seg, why);
   if (st != RS_OK) return st;
   p->total = p->seg.bytes;
   return RS_OK;

@@ -461,7 +461,13 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
   constexpr int BINS = 1 << BITS;
   constexpr int CPT = (BINS + BLOCK - 1) / BLOCK;  // cells per thread
   constexpr int STAGE = TILE * (sizeof(K) > 4 ? (int)sizeof(K) : 4);
+  // Values get their own staging (keys and values written in one sweep)
+  // when that keeps LDS within two workgroups per CU on wide tiles; else
+  // they reuse the key staging after the keys are written.
+  constexpr bool JOINT = PAIRS && BLOCK >= 512 &&
+                         STAGE + TILE * 4 + (WAVES + 2) * BINS * 4 <= 80 * 1024;
   __shared__ __align__(16) unsigned char stage_raw[STAGE];
+  __shared__ uint32_t stage_jv[JOINT ? TILE : 1];
   __shared__ uint32_t wcnt[WAVES][BINS];  // per-wave counts, then per-wave offsets
   __shared__ uint32_t tstart[BINS];       // tile-local start of each cell
   __shared__ uint32_t gdelta[BINS];       // output index - tile-local index
@@ -486,6 +492,20 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
   if (!sp.valid) return;  // uniform
   const uint64_t elem0 = sp.elem0, end = sp.end, out_base = sp.base, limit = sp.limit;
   const bool first_tile = id == 0;
+
+  // ---- prescanned: this tile's output offset of each cell, relative to
+  // its array, loaded together with the keys so that the tile waits for
+  // memory once
+  uint32_t rel[CPT];
+  if constexpr (MODE != kChained) {
+    const uint32_t rel0 = MODE == kPrescannedSeg ? p.tile_offsets[sp.block] : 0u;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      const uint32_t d = t + c * BLOCK;
+      // wraps consistently in 32 bits: the difference is below 2^30
+      rel[c] = d < p.bins ? p.tile_offsets[sp.entry0 + (uint64_t)d * sp.estride] - rel0 : 0u;
+    }
+  }
 
   // ---- load: keys and values of this thread, striped by rounds
   K k[KPT];
@@ -528,6 +548,8 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
     const uint32_t lpos = tstart[dg[r]] + wcnt[wave][dg[r]] + rk[r];
     rk[r] = lpos;
     if (valid) stage_k[lpos] = k[r];
+    if constexpr (JOINT)
+      if (valid) stage_jv[lpos] = v[r];
   }
 
   // ---- each cell's output offset for this tile, relative to its array
@@ -543,17 +565,14 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
         }
         gdelta[d] = p.digit_start[d] + excl - tstart[d];
       } else {
-        // wraps consistently in 32 bits: the difference is below 2^30
-        uint32_t rel = p.tile_offsets[sp.entry0 + (uint64_t)d * sp.estride];
-        if constexpr (MODE == kPrescannedSeg) rel -= p.tile_offsets[sp.block];
-        gdelta[d] = rel - tstart[d];
+        gdelta[d] = rel[c] - tstart[d];
       }
     }
   }
   __syncthreads();
 
-  // ---- write keys: consecutive LDS entries of one cell go to consecutive
-  // output addresses
+  // ---- write keys (and values): consecutive LDS entries of one cell go
+  // to consecutive output addresses
   const uint32_t count = (uint32_t)(end - elem0);
 #pragma unroll
   for (int r = 0; r < KPT; ++r) {
@@ -563,10 +582,13 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
       const uint32_t d = p.digit(key);
       dg[r] = d;
       const uint64_t at = out_base + gdelta[d] + i;
-      if (at < limit) kout[at] = key;
+      if (at < limit) {
+        kout[at] = key;
+        if constexpr (JOINT) vout[at] = stage_jv[i];
+      }
     }
   }
-  if constexpr (PAIRS) {
+  if constexpr (PAIRS && !JOINT) {
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < KPT; ++r)

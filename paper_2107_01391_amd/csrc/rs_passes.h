@@ -19,13 +19,13 @@ namespace rs {
 
 constexpr int kTilesPerHistBlock = 8;
 
-template <typename K, class Digit, int BITS, bool SEG>
+template <typename K, class Digit, int BITS, int BLOCK, bool SEG>
 rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const K *src, K *dst,
                           const uint32_t *srcv, uint32_t *dstv, uint64_t n, uint64_t ntiles_bound,
                           uint32_t *table, uint32_t *sums, const TileDesc *tiles, const uint32_t *ntotal,
                           hipStream_t stream) {
-  constexpr int KPT = sizeof(K) >= 16 ? 8 : 16;  // LDS staging of one tile: 32 KiB at most
-  constexpr int TILE = 256 * KPT;
+  constexpr int KPT = sizeof(K) >= 16 ? 8 : 16;  // LDS staging: 32 KiB per 256 threads
+  constexpr int TILE = BLOCK * KPT;
   constexpr int TPW = kTilesPerHistBlock;
   rs_status st;
   const uint64_t count = (uint64_t)cells * ntiles_bound;
@@ -68,22 +68,34 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
   pp.tiles = tiles;
   pp.ntotal = ntotal;
   constexpr int MODE = SEG ? kPrescannedSeg : kPrescanned;
-  const dim3 grid((uint32_t)((ntiles_bound + 7) / 8 * 8)), blk(256);
+  const dim3 grid((uint32_t)((ntiles_bound + 7) / 8 * 8)), blk(BLOCK);
   if (pairs)
     RS_TIMED("rs_rank_scatter", stream,
-             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, true, MODE>), grid, blk, 0, stream, pp,
+             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, BLOCK, KPT, true, MODE>), grid, blk, 0, stream, pp,
                                 src, dst, srcv, dstv));
   else
     RS_TIMED("rs_rank_scatter", stream,
-             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, 256, KPT, false, MODE>), grid, blk, 0, stream, pp,
+             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, BLOCK, KPT, false, MODE>), grid, blk, 0, stream, pp,
                                 src, dst, nullptr, nullptr));
   return check_launch("rs_rank_scatter");
+}
+
+// Calls f.template operator()<BLOCK>() with the plan's tile width: 512
+// threads (8192 keys per tile) or 256.  Wide tiles make each cell's run of
+// output per tile longer, so fewer output lines are written in part; keys
+// of 16 bytes keep 256 threads (LDS staging).
+template <typename K, int BITS, class F>
+rs_status with_block(uint32_t block, F &&f) {
+  if constexpr (sizeof(K) <= 8 && BITS <= 10) {
+    if (block == 512) return f.template operator()<512>();
+  }
+  return f.template operator()<256>();
 }
 
 // Runs passes [0, P) (least significant first) from keys_in to keys_out,
 // ping-ponging through alt; the last pass writes keys_out.  When the input
 // is the output and P is odd, the input is first copied to alt.
-template <typename K, class Digit, int BITS, bool SEG>
+template <typename K, class Digit, int BITS, int BLOCK, bool SEG>
 rs_status prescanned_passes(const Plan &p, const Digit *digits, uint32_t P, const void *keys_in, void *keys_out,
                             const uint32_t *vals_in, uint32_t *vals_out, void *alt_keys, uint32_t *alt_vals,
                             uint64_t n, uint64_t ntiles_bound, uint32_t *table, uint32_t *sums,
@@ -110,8 +122,9 @@ rs_status prescanned_passes(const Plan &p, const Digit *digits, uint32_t P, cons
     const bool to_x = ((P - 1 - i) % 2) == 0;
     K *dst = to_x ? X : Y;
     uint32_t *dstv = to_x ? XV : YV;
-    rs_status st = prescanned_pass<K, Digit, BITS, SEG>(digits[i], p.pass_cells[i], pairs, src, dst, srcv, dstv, n,
-                                                         ntiles_bound, table, sums, tiles, ntotal, stream);
+    rs_status st = prescanned_pass<K, Digit, BITS, BLOCK, SEG>(digits[i], p.pass_cells[i], pairs, src, dst, srcv,
+                                                                dstv, n, ntiles_bound, table, sums, tiles, ntotal,
+                                                                stream);
     if (st != RS_OK) return st;
     src = dst;
     srcv = dstv;

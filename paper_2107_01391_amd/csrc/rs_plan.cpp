@@ -205,9 +205,11 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     return RS_ERR_UNSUPPORTED;
   }
 
-  // tile shape: 256 threads; keys per thread sized so that the LDS staging
-  // of one tile stays at 32 KiB for wide keys
-  p.block = 256;
+  // tile shape: 256 threads (chained), or the tuned width (prescanned);
+  // keys per thread sized so that the LDS staging of one tile stays at
+  // 32 KiB per 256 threads for wide keys
+  p.prescanned = !p.literal && n >= tune.prescan_min_n;
+  p.block = p.prescanned ? prescan_block(tune, k.key_bytes, p.bits) : 256;
   p.kpt = k.key_bytes >= 16 ? 8 : 16;
   p.tile = p.block * p.kpt;
   p.ntiles = (n + p.tile - 1) / p.tile;
@@ -219,8 +221,6 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
   if (g < 1) g = 1;
   p.hist_grid = (uint32_t)g;
   p.hist_copies = count_copies((uint32_t)words, kLdsCountBudget);
-
-  p.prescanned = !p.literal && n >= tune.prescan_min_n;
 
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -258,8 +258,12 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
   return RS_OK;
 }
 
+uint32_t prescan_block(const Tuning &tune, uint32_t key_bytes, uint32_t bits) {
+  return (key_bytes <= 8 && bits <= 10 && tune.tile_block == 512) ? 512u : 256u;
+}
+
 rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint32_t nseg, bool own_alt,
-                          SegLayout *Lp, std::string *why) {
+                          uint32_t block, SegLayout *Lp, std::string *why) {
   SegLayout &L = *Lp;
   L = SegLayout();
   if (nseg == 0) {
@@ -275,8 +279,9 @@ rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint3
   L.total = total;
   L.nseg = nseg;
   L.own_alt = own_alt;
-  L.tile = kb >= 16 ? 2048 : 4096;
-  L.small_max = L.tile;
+  L.block = kb <= 8 && block == 512 ? 512 : 256;
+  L.tile = L.block * (kb >= 16 ? 8 : 16);
+  L.small_max = kb >= 16 ? 2048 : 4096;  // one workgroup of 256 threads sorts it in LDS
   // a large array spans more than one tile, so there are at most
   // total / tile of them, each adding at most one partial tile
   const uint64_t full = (total + L.tile - 1) / L.tile;

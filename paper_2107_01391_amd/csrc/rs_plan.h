@@ -40,6 +40,7 @@ struct Tuning {
   uint32_t digit_bits = 8;       // target width of a pass (power-of-two bases)
   uint32_t max_cells = 1024;     // largest count space of one pass (other bases)
   uint64_t prescan_min_n = 3ull << 20;  // single arrays from this size use prescanned passes
+  uint32_t tile_block = 512;            // threads per tile of prescanned passes (256 or 512)
 };
 
 // Scratch layout of the segmented form over `nseg` arrays holding `total`
@@ -49,7 +50,7 @@ struct SegLayout {
   uint32_t npasses = 0;
   uint64_t total = 0;
   uint32_t nseg = 0;
-  uint32_t tile = 4096, small_max = 4096;
+  uint32_t block = 256, tile = 4096, small_max = 4096;
   uint64_t tiles_bound = 0;  // large-array tiles, at most
   uint32_t small_grid = 1;
   bool own_alt = false;
@@ -95,9 +96,12 @@ struct Plan {
 rs_status key_info(const rs_key_desc *desc, KeyInfo *ki, std::string *why);
 rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tuning &tune, Plan *plan,
                     std::string *why);
+// Threads per tile of prescanned passes for keys of `key_bytes` and passes
+// of kernel variant `bits` (the choice with_block() makes on the device side).
+uint32_t prescan_block(const Tuning &tune, uint32_t key_bytes, uint32_t bits);
 // Layout of the segmented form for passes [0, npasses) of `p`.
 rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint32_t nseg, bool own_alt,
-                          SegLayout *L, std::string *why);
+                          uint32_t block, SegLayout *L, std::string *why);
 
 constexpr uint32_t kScanBlock = 256;
 constexpr uint32_t kScanItems = 8;

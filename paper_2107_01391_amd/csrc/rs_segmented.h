@@ -68,9 +68,11 @@ rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, 
   if ((st = check_launch("rs_small_sort")) != RS_OK) return st;
 
   // large arrays: the passes, every array sharing each launch
-  return prescanned_passes<K, Digit, BITS, true>(p, digits, P, keys_in, keys_out, vals_in, vals_out, alt_keys,
-                                                 alt_vals, L.total, L.tiles_bound, table, sums, tiles, ntotal,
-                                                 stream);
+  return with_block<K, BITS>(L.block, [&]<int BLOCK>() {
+    return prescanned_passes<K, Digit, BITS, BLOCK, true>(p, digits, P, keys_in, keys_out, vals_in, vals_out,
+                                                          alt_keys, alt_vals, L.total, L.tiles_bound, table, sums,
+                                                          tiles, ntotal, stream);
+  });
 }
 
 }  // namespace rs

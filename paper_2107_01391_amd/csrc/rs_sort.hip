@@ -170,10 +170,12 @@ template <typename K, class Digit, int BITS>
 static rs_status run_prescanned(const Plan &pl, const Digit *digits, const void *keys_in, void *keys_out,
                                 const uint32_t *vals_in, uint32_t *vals_out, void *tmp, hipStream_t stream) {
   char *base = (char *)tmp;
-  return prescanned_passes<K, Digit, BITS, false>(
-      pl, digits, pl.npasses, keys_in, keys_out, vals_in, vals_out, base + pl.off_keys_alt,
-      pl.pairs ? (uint32_t *)(base + pl.off_vals_alt) : nullptr, pl.n, pl.ntiles, (uint32_t *)(base + pl.off_table),
-      (uint32_t *)(base + pl.off_sums), nullptr, nullptr, stream);
+  return with_block<K, BITS>(pl.block, [&]<int BLOCK>() {
+    return prescanned_passes<K, Digit, BITS, BLOCK, false>(
+        pl, digits, pl.npasses, keys_in, keys_out, vals_in, vals_out, base + pl.off_keys_alt,
+        pl.pairs ? (uint32_t *)(base + pl.off_vals_alt) : nullptr, pl.n, pl.ntiles,
+        (uint32_t *)(base + pl.off_table), (uint32_t *)(base + pl.off_sums), nullptr, nullptr, stream);
+  });
 }
 
 template <typename K, class Digit, int BITS>

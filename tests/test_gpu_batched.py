@@ -59,9 +59,16 @@ def _cmp(gk, gv, ok, ov, offs):
             assert np.array_equal(gv[a:b], ov[a:b]), f"array {i} ({b - a} keys): values differ"
 
 
+@pytest.fixture(params=[256, 512], ids=["tile256", "tile512"])
+def tile_block(request, monkeypatch):
+    """Both tile widths of the large arrays' passes (4096 and 8192 keys)."""
+    monkeypatch.setenv("RS_TILE_BLOCK", str(request.param))
+    yield request.param
+
+
 @pytest.mark.parametrize("count,lo,hi", [(1, 1, 1), (1, 5000, 5000), (7, 1, 300), (64, 1, 40_000),
                                          (300, 1024, 65_536), (16, 100_000, 400_000)])
-def test_batched_u32_pairs(count, lo, hi):
+def test_batched_u32_pairs(tile_block, count, lo, hi):
     _say(f"batched u32 pairs count={count} sizes [{lo}, {hi}]")
     keys, vals, offs = workloads.batched_u32(count=count, lo=lo, hi=hi)
     gk, gv = gpu_batched(keys, vals, offs, "u32", 256, 4)
@@ -69,9 +76,9 @@ def test_batched_u32_pairs(count, lo, hi):
     _cmp(gk, gv, ok, ov, offs)
 
 
-def test_batched_with_empty_and_single_arrays():
-    _say("batched with empty arrays")
-    sizes = np.array([0, 1, 0, 4096, 4097, 0, 2, 12_000, 0], np.int64)
+def test_batched_with_empty_and_single_arrays(tile_block):
+    _say(f"batched with empty arrays, tile block {tile_block}")
+    sizes = np.array([0, 1, 0, 4096, 4097, 0, 2, 12_000, 0, 8192, 8193, 16_384, 24_577], np.int64)
     offs = np.zeros(sizes.shape[0] + 1, np.uint64)
     offs[1:] = np.cumsum(sizes)
     rng = np.random.default_rng(5)
@@ -82,7 +89,7 @@ def test_batched_with_empty_and_single_arrays():
     _cmp(gk, gv, ok, ov, offs)
 
 
-def test_batched_keys_only():
+def test_batched_keys_only(tile_block):
     _say("batched keys only")
     keys, _, offs = workloads.batched_u32(count=40, lo=10, hi=30_000)
     gk, _ = gpu_batched(keys, None, offs, "u32", 256, 4)
@@ -98,7 +105,7 @@ def test_batched_in_place():
     _cmp(gk, gv, ok, ov, offs)
 
 
-def test_batched_fixed_point_and_strings():
+def test_batched_fixed_point_and_strings(tile_block):
     _say("batched fixed point")
     w = workloads.fixed_point_decimals(60_000)
     offs = np.array([0, 10, 4000, 4100, 30_000, 60_000], np.uint64)

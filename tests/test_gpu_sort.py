@@ -278,12 +278,43 @@ def test_prescanned_hot_cells(prescanned, distinct):
     assert_same(gk, gv, ok, ov)
 
 
+@pytest.mark.parametrize("kind,n", [("u32", 1), ("u32", 8191), ("u32", 8192), ("u32", 8193), ("u32", 5 * 8192 + 3),
+                                    ("u32", 1 << 20), ("u64", 70_001), ("fixed_i64", 100_003)])
+def test_prescanned_wide_tiles(prescanned, monkeypatch, kind, n):
+    """512-thread tiles (8192 keys) for 4- and 8-byte keys."""
+    monkeypatch.setenv("RS_TILE_BLOCK", "512")
+    _say(f"prescanned wide tiles {kind} n={n}")
+    if kind == "u32":
+        w = workloads.uniform_u32_pairs(n)
+        args = ("u32", 256, 4)
+        keys, vals = w.keys, w.vals
+    elif kind == "u64":
+        rng = np.random.default_rng(9)
+        keys = rng.integers(0, 2**64, n, dtype=np.uint64)
+        vals = np.arange(n, dtype=np.uint32)
+        args = ("u64", 256, 8)
+    else:
+        w = workloads.fixed_point_decimals(n)
+        keys, vals = w.keys, w.vals
+        args = ("fixed_i64", 10, 9)
+    gk, gv = gpu_sort(keys, vals, *args)
+    ok, ov = oracle_sort(keys, vals, *args)
+    assert_same(gk, gv, ok, ov, f"n={n}")
+    gk, gv = gpu_sort(keys, vals, *args, in_place=True)
+    assert_same(gk, gv, ok, ov, f"in place n={n}")
+    gk, _ = gpu_sort(keys, None, *args)
+    assert_same(gk, None, ok, None, f"keys only n={n}")
+
+
+@pytest.mark.parametrize("tile_block", [256, 512])
 @pytest.mark.parametrize("base,ndims,bits", [(16, 8, 4), (2, 32, 11), (4, 16, 10)])
-def test_prescanned_digit_widths(prescanned, monkeypatch, base, ndims, bits):
+def test_prescanned_digit_widths(prescanned, monkeypatch, tile_block, base, ndims, bits):
     """Other pass widths on power-of-two bases: 8 passes of 16 cells; passes
-    of 2048, 2048 and 1024 cells; 1024-cell passes."""
+    of 2048, 2048 and 1024 cells (2048-cell passes keep 256-thread tiles
+    whatever the tuning asks); 1024-cell passes."""
     monkeypatch.setenv("RS_DIGIT_BITS", str(bits))
-    _say(f"prescanned base {base} digit bits {bits}")
+    monkeypatch.setenv("RS_TILE_BLOCK", str(tile_block))
+    _say(f"prescanned base {base} digit bits {bits} tile block {tile_block}")
     w = workloads.uniform_u32_pairs(123_457)
     gk, gv = gpu_sort(w.keys, w.vals, "u32", base, ndims)
     ok, ov = oracle_sort(w.keys, w.vals, "u32", base, ndims)
