@@ -15,6 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librs.so")
 
 RS_OK = 0
+RS_ERR_NULL_ARG = 1
 RS_KEY_U32, RS_KEY_U64, RS_KEY_FIXED_I64, RS_KEY_STR = 0, 1, 2, 3
 RS_FLAG_VALIDATE = 1
 RS_MAX_ELEMENTS = (1 << 30) - 1
@@ -22,7 +23,10 @@ RS_MAX_ELEMENTS = (1 << 30) - 1
 KINDS = {"u32": RS_KEY_U32, "u64": RS_KEY_U64, "fixed_i64": RS_KEY_FIXED_I64, "str": RS_KEY_STR}
 
 EXPORTED = ["rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_batched_temp_bytes", "rs_sort_batched",
-            "rs_status_string", "rs_last_error", "rs_prof_enable", "rs_prof_query"]
+            "rs_status_string", "rs_last_error", "rs_prof_enable", "rs_prof_query",
+            "rs_tuning_get", "rs_tuning_set", "rs_tuning_clear", "rs_tune_temp_bytes", "rs_tune_sort",
+            "rs_tune_batched", "rs_tuning_save", "rs_tuning_load",
+            "rs_graph_sort", "rs_graph_sort_batched", "rs_graph_launch", "rs_graph_destroy"]
 
 
 class RSError(RuntimeError):
@@ -42,6 +46,15 @@ def key_desc(kind: str | int, base: int = 0, ndims: int = 0, frac_digits: int = 
     if k == RS_KEY_STR and not str_width:
         str_width = 16
     return KeyDesc(k, base, ndims, frac_digits, str_width, RS_FLAG_VALIDATE if validate else 0)
+
+
+class Tuning(ctypes.Structure):
+    """rs_tuning: how the digits are grouped into passes and the tile shape."""
+    _fields_ = [("digit_bits", ctypes.c_uint32), ("max_cells", ctypes.c_uint32), ("tile_block", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("prescan_min_n", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 _lib = None
@@ -74,6 +87,26 @@ def load_library(path: str | None = None):
     lib.rs_prof_enable.restype = ctypes.c_int
     lib.rs_prof_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)]
     lib.rs_prof_query.restype = ctypes.c_int
+    tp = ctypes.POINTER(Tuning)
+    dbl = ctypes.POINTER(ctypes.c_double)
+    ci = ctypes.c_int
+    lib.rs_tuning_get.argtypes = [dp, u64, ci, ci, tp]
+    lib.rs_tuning_set.argtypes = [dp, u64, ci, ci, tp]
+    lib.rs_tuning_clear.argtypes = []
+    lib.rs_tune_temp_bytes.argtypes = [dp, u64, u32, ci, ctypes.POINTER(sz)]
+    lib.rs_tune_sort.argtypes = [dp, vp, vp, vp, vp, u64, vp, sz, vp, u32, tp, dbl]
+    lib.rs_tune_batched.argtypes = [dp, vp, vp, vp, vp, vp, u32, u64, vp, sz, vp, u32, tp, dbl]
+    lib.rs_tuning_save.argtypes = [ctypes.c_char_p]
+    lib.rs_tuning_load.argtypes = [ctypes.c_char_p]
+    gp = ctypes.POINTER(vp)
+    lib.rs_graph_sort.argtypes = [dp, vp, vp, vp, vp, u64, vp, sz, gp]
+    lib.rs_graph_sort_batched.argtypes = [dp, vp, vp, vp, vp, vp, u32, u64, vp, sz, gp]
+    lib.rs_graph_launch.argtypes = [vp, vp]
+    lib.rs_graph_destroy.argtypes = [vp]
+    for f in ("rs_tuning_get", "rs_tuning_set", "rs_tuning_clear", "rs_tune_temp_bytes", "rs_tune_sort",
+              "rs_tune_batched", "rs_tuning_save", "rs_tuning_load", "rs_graph_sort", "rs_graph_sort_batched",
+              "rs_graph_launch", "rs_graph_destroy"):
+        getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -152,3 +185,96 @@ def rs_prof_query(name: str) -> tuple[int, float]:
     ms = ctypes.c_double(0.0)
     _check(load_library().rs_prof_query(name.encode(), ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+# ------------------------------------------------------------------ tuning
+
+def rs_tuning_get(desc: KeyDesc, n: int, with_values: bool, batched: bool = False) -> Tuning:
+    t = Tuning()
+    _check(load_library().rs_tuning_get(ctypes.byref(desc), n, int(bool(with_values)), int(bool(batched)),
+                                        ctypes.byref(t)))
+    return t
+
+
+def rs_tuning_set(desc: KeyDesc, n: int, with_values: bool, batched: bool, t: Tuning) -> None:
+    _check(load_library().rs_tuning_set(ctypes.byref(desc), n, int(bool(with_values)), int(bool(batched)),
+                                        ctypes.byref(t)))
+
+
+def rs_tuning_clear() -> None:
+    _check(load_library().rs_tuning_clear())
+
+
+def rs_tune_temp_bytes(desc: KeyDesc, n: int, nseg: int, with_values: bool) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().rs_tune_temp_bytes(ctypes.byref(desc), n, nseg, int(bool(with_values)), ctypes.byref(out)))
+    return out.value
+
+
+def rs_tune_sort(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, n: int, tmp, tmp_bytes: int, stream=None,
+                 reps: int = 3) -> tuple[Tuning, float]:
+    t, ms = Tuning(), ctypes.c_double(0.0)
+    _check(load_library().rs_tune_sort(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                       _ptr(vals_out), n, _ptr(tmp), tmp_bytes, _stream(stream), reps,
+                                       ctypes.byref(t), ctypes.byref(ms)))
+    return t, ms.value
+
+
+def rs_tune_batched(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, nseg: int, total: int, tmp,
+                    tmp_bytes: int, stream=None, reps: int = 3) -> tuple[Tuning, float]:
+    t, ms = Tuning(), ctypes.c_double(0.0)
+    _check(load_library().rs_tune_batched(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                          _ptr(vals_out), _ptr(d_seg_offsets), nseg, total, _ptr(tmp), tmp_bytes,
+                                          _stream(stream), reps, ctypes.byref(t), ctypes.byref(ms)))
+    return t, ms.value
+
+
+def rs_tuning_save(path: str) -> None:
+    _check(load_library().rs_tuning_save(path.encode()))
+
+
+def rs_tuning_load(path: str) -> None:
+    _check(load_library().rs_tuning_load(path.encode()))
+
+
+# ------------------------------------------------------------------ graphs
+
+class Graph:
+    """A captured sort (rs_graph); replay with launch(), free with close()."""
+
+    def __init__(self, handle: int, keep: tuple):
+        self._h = handle
+        self._keep = keep  # the buffers the graph points at stay alive with it
+
+    def launch(self, stream=None) -> None:
+        if not self._h:
+            raise RSError(RS_ERR_NULL_ARG, "graph is closed")
+        _check(load_library().rs_graph_launch(self._h, _stream(stream)))
+
+    def close(self) -> None:
+        if self._h:
+            _check(load_library().rs_graph_destroy(self._h))
+            self._h = None
+            self._keep = ()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rs_graph_sort(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, n: int, tmp, tmp_bytes: int) -> Graph:
+    h = ctypes.c_void_p(None)
+    _check(load_library().rs_graph_sort(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                        _ptr(vals_out), n, _ptr(tmp), tmp_bytes, ctypes.byref(h)))
+    return Graph(h.value, (keys_in, keys_out, vals_in, vals_out, tmp))
+
+
+def rs_graph_sort_batched(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, nseg: int, total: int,
+                          tmp, tmp_bytes: int) -> Graph:
+    h = ctypes.c_void_p(None)
+    _check(load_library().rs_graph_sort_batched(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                                _ptr(vals_out), _ptr(d_seg_offsets), nseg, total, _ptr(tmp),
+                                                tmp_bytes, ctypes.byref(h)))
+    return Graph(h.value, (keys_in, keys_out, vals_in, vals_out, d_seg_offsets, tmp))

@@ -8,15 +8,16 @@ namespace rs {
 
 // The dimension groups come from the single-array planner; the segmented
 // form sorts every group of every array (least significant first).
-static rs_status make_batched(const rs_key_desc *desc, uint64_t total, uint32_t nseg, bool pairs, Plan *p,
-                              std::string *why) {
-  const Tuning tune = current_tuning(desc, total, pairs);
+rs_status make_batched(const rs_key_desc *desc, uint64_t total, uint64_t extent, uint32_t nseg, bool pairs,
+                       Plan *p, std::string *why) {
+  const Tuning tune = current_tuning(desc, total, pairs, true);
   rs_status st = make_plan(desc, 1, true, tune, p, why);
   if (st != RS_OK) return st;
   p->pairs = pairs;
   p->literal = false;
   p->prescanned = false;
-  st = make_seg_layout(*p, p->npasses, total, nseg, true, prescan_block(tune, p->key.key_bytes, p->bits), &p->seg, why);
+  st = make_seg_layout(*p, p->npasses, total, extent, nseg, true, prescan_block(tune, p->key.key_bytes, p->bits),
+                       &p->seg, why);
   if (st != RS_OK) return st;
   p->total = p->seg.bytes;
   return RS_OK;
@@ -24,22 +25,40 @@ static rs_status make_batched(const rs_key_desc *desc, uint64_t total, uint32_t 
 
 template <typename K, class Digit>
 static rs_status batched_bits(const Plan &p, const Digit *d, const void *ki, void *ko, const uint32_t *vi,
-                              uint32_t *vo, const uint64_t *off, void *tmp, hipStream_t s) {
+                              uint32_t *vo, const uint64_t *lo, const uint64_t *hi, void *tmp, hipStream_t s) {
   char *base = (char *)tmp;
   void *ak = base + p.seg.off_alt_keys;
   uint32_t *av = vi ? (uint32_t *)(base + p.seg.off_alt_vals) : nullptr;
   if constexpr (sizeof(K) >= 16) {  // strings: 27^2 = 729 cells per pass
     if (p.bits != 10) return fail(RS_ERR_UNSUPPORTED, "string passes use 10-bit cells");
-    return run_segmented<K, Digit, 10>(p, p.seg, d, ki, ko, vi, vo, ak, av, off, base, s);
+    return run_segmented<K, Digit, 10>(p, p.seg, d, ki, ko, vi, vo, ak, av, lo, hi, base, s);
   }
   switch (p.bits) {
   case 8:
-    return run_segmented<K, Digit, 8>(p, p.seg, d, ki, ko, vi, vo, ak, av, off, base, s);
+    return run_segmented<K, Digit, 8>(p, p.seg, d, ki, ko, vi, vo, ak, av, lo, hi, base, s);
   case 10:
-    return run_segmented<K, Digit, 10>(p, p.seg, d, ki, ko, vi, vo, ak, av, off, base, s);
+    return run_segmented<K, Digit, 10>(p, p.seg, d, ki, ko, vi, vo, ak, av, lo, hi, base, s);
   default:
-    return run_segmented<K, Digit, 11>(p, p.seg, d, ki, ko, vi, vo, ak, av, off, base, s);
+    return run_segmented<K, Digit, 11>(p, p.seg, d, ki, ko, vi, vo, ak, av, lo, hi, base, s);
   }
+}
+
+rs_status batched_run(const Plan &p, const void *ki, void *ko, const uint32_t *vi, uint32_t *vo,
+                      const uint64_t *seg_lo, const uint64_t *seg_hi, void *tmp, hipStream_t s) {
+  const uint32_t kb = p.key.key_bytes;
+  switch (p.mode) {
+  case kModePow2:
+    if (kb == 4) return batched_bits<uint32_t, DigitPow2>(p, p.p2, ki, ko, vi, vo, seg_lo, seg_hi, tmp, s);
+    return batched_bits<uint64_t, DigitPow2>(p, p.p2, ki, ko, vi, vo, seg_lo, seg_hi, tmp, s);
+  case kModeDiv32:
+    if (kb == 4) return batched_bits<uint32_t, DigitDiv32>(p, p.d32, ki, ko, vi, vo, seg_lo, seg_hi, tmp, s);
+    return batched_bits<uint64_t, DigitDiv32>(p, p.d32, ki, ko, vi, vo, seg_lo, seg_hi, tmp, s);
+  case kModeDiv64:
+    return batched_bits<uint64_t, DigitDiv64>(p, p.d64, ki, ko, vi, vo, seg_lo, seg_hi, tmp, s);
+  case kModeStr16:
+    return batched_bits<Str16, DigitStr16>(p, p.s16, ki, ko, vi, vo, seg_lo, seg_hi, tmp, s);
+  }
+  return fail(RS_ERR_BAD_DESC, "unknown digit mode");
 }
 
 }  // namespace rs
@@ -54,7 +73,7 @@ rs_status rs_batched_temp_bytes(const rs_key_desc *desc, uint64_t total, uint32_
   if (!bytes) return fail(RS_ERR_NULL_ARG, "bytes is NULL");
   Plan p;
   std::string why;
-  rs_status st = make_batched(desc, total, nseg, with_values != 0, &p, &why);
+  rs_status st = make_batched(desc, total, total, nseg, with_values != 0, &p, &why);
   if (st != RS_OK) return fail(st, why);
   *bytes = p.total;
   return RS_OK;
@@ -72,7 +91,7 @@ rs_status rs_sort_batched(const rs_key_desc *desc, const void *keys_in, void *ke
   if (pairs && !vals_out) return fail(RS_ERR_NULL_ARG, "vals_out is required with vals_in");
   Plan p;
   std::string why;
-  rs_status st = make_batched(desc, total, nseg, pairs, &p, &why);
+  rs_status st = make_batched(desc, total, total, nseg, pairs, &p, &why);
   if (st != RS_OK) return fail(st, why);
   if (tmp_bytes < p.total)
     return fail(RS_ERR_TMP_TOO_SMALL, "tmp_bytes " + std::to_string(tmp_bytes) + " < " + std::to_string(p.total));
@@ -83,24 +102,8 @@ rs_status rs_sort_batched(const rs_key_desc *desc, const void *keys_in, void *ke
     st = validate_keys(p, keys_in, total, tmp, s);
     if (st != RS_OK) return st;
   }
-  const uint32_t kb = p.key.key_bytes;
-  switch (p.mode) {
-  case kModePow2:
-    if (kb == 4) return batched_bits<uint32_t, DigitPow2>(p, p.p2, keys_in, keys_out, vals_in, vals_out,
-                                                          d_seg_offsets, tmp, s);
-    return batched_bits<uint64_t, DigitPow2>(p, p.p2, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, tmp, s);
-  case kModeDiv32:
-    if (kb == 4) return batched_bits<uint32_t, DigitDiv32>(p, p.d32, keys_in, keys_out, vals_in, vals_out,
-                                                           d_seg_offsets, tmp, s);
-    return batched_bits<uint64_t, DigitDiv32>(p, p.d32, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, tmp,
-                                              s);
-  case kModeDiv64:
-    return batched_bits<uint64_t, DigitDiv64>(p, p.d64, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, tmp,
-                                              s);
-  case kModeStr16:
-    return batched_bits<Str16, DigitStr16>(p, p.s16, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, tmp, s);
-  }
-  return fail(RS_ERR_BAD_DESC, "unknown digit mode");
+  // array i is [offsets[i], offsets[i + 1])
+  return batched_run(p, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, d_seg_offsets + 1, tmp, s);
 }
 
 }  // extern "C"

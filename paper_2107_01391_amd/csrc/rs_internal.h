@@ -33,8 +33,18 @@ void prof_end(void *token, hipStream_t s);
     ::rs::prof_end(rs_tok_, STREAM);                                        \
   } while (0)
 
-// Tile and digit-width choices for a description and size: the autotuner's
-// cached choice when one exists, else the defaults.
-Tuning current_tuning(const rs_key_desc *desc, uint64_t n, bool pairs);
+// Tile and digit-width choices for a description and size (`batched`: the
+// segmented form over `n` keys in all): environment overrides, else the
+// autotuner's cached choice for the size class, else the defaults.
+Tuning current_tuning(const rs_key_desc *desc, uint64_t n, bool pairs, bool batched = false);
+
+// Batched form: plan over arrays holding `total` keys within `extent`
+// elements, and the launch sequence over arrays [seg_lo[i], seg_hi[i]).
+rs_status make_batched(const rs_key_desc *desc, uint64_t total, uint64_t extent, uint32_t nseg, bool pairs,
+                       Plan *p, std::string *why);
+rs_status batched_run(const Plan &p, const void *ki, void *ko, const uint32_t *vi, uint32_t *vo,
+                      const uint64_t *seg_lo, const uint64_t *seg_hi, void *tmp, hipStream_t s);
+// Device copy by a kernel (capturable in a graph).
+rs_status launch_copy(void *dst, const void *src, size_t bytes, hipStream_t stream);
 
 }  // namespace rs

@@ -33,6 +33,11 @@ namespace rs {
 
 // ------------------------------------------------------------------ fill
 
+// Plain copy in 4-byte words (the in-place start of an odd pass count).
+static __global__ void rs_copy(uint32_t *__restrict__ dst, const uint32_t *__restrict__ src, uint64_t n4) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (uint64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
 static __global__ void rs_fill(uint4 *__restrict__ p, uint64_t n16, uint32_t value) {
   const uint4 v = make_uint4(value, value, value, value);
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (uint64_t)gridDim.x * blockDim.x)

@@ -108,21 +108,20 @@ rs_status prescanned_passes(const Plan &p, const Digit *digits, uint32_t P, cons
   const K *src = (const K *)keys_in;
   const uint32_t *srcv = vals_in;
   const bool odd = P % 2 == 1;
+  rs_status st;
   if (odd && keys_in == keys_out) {
-    if (hipMemcpyAsync(Y, keys_in, n * p.key.key_bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)
-      return fail(RS_ERR_HIP, "hipMemcpyAsync");
+    if ((st = launch_copy(Y, keys_in, n * p.key.key_bytes, stream)) != RS_OK) return st;
     src = Y;
   }
   if (pairs && odd && vals_in == vals_out) {
-    if (hipMemcpyAsync(YV, vals_in, n * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
-      return fail(RS_ERR_HIP, "hipMemcpyAsync");
+    if ((st = launch_copy(YV, vals_in, n * 4, stream)) != RS_OK) return st;
     srcv = YV;
   }
   for (uint32_t i = 0; i < P; ++i) {
     const bool to_x = ((P - 1 - i) % 2) == 0;
     K *dst = to_x ? X : Y;
     uint32_t *dstv = to_x ? XV : YV;
-    rs_status st = prescanned_pass<K, Digit, BITS, BLOCK, SEG>(digits[i], p.pass_cells[i], pairs, src, dst, srcv,
+    st = prescanned_pass<K, Digit, BITS, BLOCK, SEG>(digits[i], p.pass_cells[i], pairs, src, dst, srcv,
                                                                 dstv, n, ntiles_bound, table, sums, tiles, ntotal,
                                                                 stream);
     if (st != RS_OK) return st;

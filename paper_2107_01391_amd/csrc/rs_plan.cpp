@@ -262,21 +262,22 @@ uint32_t prescan_block(const Tuning &tune, uint32_t key_bytes, uint32_t bits) {
   return (key_bytes <= 8 && bits <= 10 && tune.tile_block == 512) ? 512u : 256u;
 }
 
-rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint32_t nseg, bool own_alt,
-                          uint32_t block, SegLayout *Lp, std::string *why) {
+rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint64_t extent, uint32_t nseg,
+                          bool own_alt, uint32_t block, SegLayout *Lp, std::string *why) {
   SegLayout &L = *Lp;
   L = SegLayout();
   if (nseg == 0) {
     *why = "nseg must be at least 1";
     return RS_ERR_BAD_DESC;
   }
-  if (total >= (1ull << 40)) {
-    *why = "total must be below 2^40";
+  if (extent >= (1ull << 40) || total > extent) {
+    *why = "total must be below 2^40 and within the extent";
     return RS_ERR_UNSUPPORTED;
   }
   const uint32_t kb = p.key.key_bytes;
   L.npasses = npasses;
   L.total = total;
+  L.extent = extent;
   L.nseg = nseg;
   L.own_alt = own_alt;
   L.block = kb <= 8 && block == 512 ? 512 : 256;
@@ -301,8 +302,8 @@ rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint3
     return at;
   };
   if (own_alt) {
-    L.off_alt_keys = take(total * kb);
-    if (p.pairs) L.off_alt_vals = take(total * 4);
+    L.off_alt_keys = take(extent * kb);
+    if (p.pairs) L.off_alt_vals = take(extent * 4);
   }
   L.off_ctrl = take(3 * 4);
   L.off_large_ids = take((size_t)nseg * 4);

@@ -48,7 +48,8 @@ struct Tuning {
 // first).  Offsets are relative to the start of the segmented region.
 struct SegLayout {
   uint32_t npasses = 0;
-  uint64_t total = 0;
+  uint64_t total = 0;   // keys in all arrays
+  uint64_t extent = 0;  // elements the arrays span (alternate arrays' size)
   uint32_t nseg = 0;
   uint32_t block = 256, tile = 4096, small_max = 4096;
   uint64_t tiles_bound = 0;  // large-array tiles, at most
@@ -100,8 +101,8 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
 // of kernel variant `bits` (the choice with_block() makes on the device side).
 uint32_t prescan_block(const Tuning &tune, uint32_t key_bytes, uint32_t bits);
 // Layout of the segmented form for passes [0, npasses) of `p`.
-rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint32_t nseg, bool own_alt,
-                          uint32_t block, SegLayout *L, std::string *why);
+rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint64_t extent, uint32_t nseg,
+                          bool own_alt, uint32_t block, SegLayout *L, std::string *why);
 
 constexpr uint32_t kScanBlock = 256;
 constexpr uint32_t kScanItems = 8;

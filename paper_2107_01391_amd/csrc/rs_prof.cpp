@@ -55,6 +55,9 @@ bool prof_on() { return prof().on.load(std::memory_order_relaxed); }
 
 void *prof_begin(const char *name, hipStream_t s) {
   Profiler &p = prof();
+  // launches being captured into a graph are not timed
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
   std::lock_guard<std::mutex> g(p.mu);
   if (!p.on) return nullptr;
   Record r{name, p.take(), p.take()};

@@ -17,8 +17,10 @@
 
 namespace rs {
 
+// Array s is elements [seg_lo[s], seg_hi[s]).  Offsets of back-to-back
+// arrays are the case seg_hi = seg_lo + 1.
 struct SegPlanParams {
-  const uint64_t *seg_off;  // [nseg + 1]
+  const uint64_t *seg_lo, *seg_hi;  // [nseg] each
   uint32_t nseg;
   uint32_t small_max;       // arrays up to this length are sorted on chip
   uint32_t tile;            // keys per tile of the large arrays
@@ -38,7 +40,7 @@ __global__ __launch_bounds__(BLOCK) void rs_seg_plan(const SegPlanParams q) {
   for (uint32_t base = 0; base < q.nseg; base += BLOCK) {
     const uint32_t s = base + t;
     uint64_t len = 0;
-    if (s < q.nseg) len = q.seg_off[s + 1] - q.seg_off[s];
+    if (s < q.nseg) len = q.seg_hi[s] - q.seg_lo[s];
     const bool in = s < q.nseg;
     const bool large = in && len > q.small_max;
     sh_large[t] = large ? 1u : 0u;
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(BLOCK) void rs_seg_plan(const SegPlanParams q) {
 }
 
 struct SegTilesParams {
-  const uint64_t *seg_off;
+  const uint64_t *seg_lo, *seg_hi;
   const uint32_t *large_ids, *tile_base, *nlarge;
   uint32_t tile;
   TileDesc *tiles;   // [tiles_bound]
@@ -89,7 +91,7 @@ static __global__ __launch_bounds__(256) void rs_seg_tiles(const SegTilesParams 
     else hi = mid;
   }
   const uint32_t sid = q.large_ids[lo];
-  const uint64_t sb = q.seg_off[sid], se = q.seg_off[sid + 1];
+  const uint64_t sb = q.seg_lo[sid], se = q.seg_hi[sid];
   TileDesc td;
   td.base = sb;
   td.len = (uint32_t)(se - sb);
@@ -105,7 +107,7 @@ struct SmallParams {
   Digit digit[kMaxPasses];
   uint32_t npasses;
   uint32_t pass_cells[kMaxPasses];
-  const uint64_t *seg_off;
+  const uint64_t *seg_lo, *seg_hi;
   const uint32_t *small_ids;
   const uint32_t *nsmall;
 };
@@ -131,8 +133,8 @@ __global__ __launch_bounds__(BLOCK) void rs_small_sort(const SmallParams<Digit> 
   const uint32_t nsmall = *sp.nsmall;
   for (uint32_t idx = blockIdx.x; idx < nsmall; idx += gridDim.x) {
     const uint32_t sid = sp.small_ids[idx];
-    const uint64_t b = sp.seg_off[sid];
-    const uint32_t len = (uint32_t)(sp.seg_off[sid + 1] - b);
+    const uint64_t b = sp.seg_lo[sid];
+    const uint32_t len = (uint32_t)(sp.seg_hi[sid] - b);
     const uint32_t wstart = wave * kWave * KPT;
     const uint32_t nvalid = wstart >= len ? 0u : (len - wstart < (uint32_t)(kWave * KPT) ? len - wstart
                                                                                           : (uint32_t)(kWave * KPT));

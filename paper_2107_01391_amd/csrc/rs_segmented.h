@@ -18,13 +18,15 @@
 
 namespace rs {
 
-// Sorts arrays [seg_off[i], seg_off[i+1]) of keys_in by passes
-// [0, L.npasses) of plan p (least significant first) into keys_out.  alt_*
-// are scratch arrays of `total` elements.
+// Sorts arrays [seg_lo[i], seg_hi[i]) of keys_in by passes [0, L.npasses)
+// of plan p (least significant first) into the same positions of keys_out.
+// The arrays lie within the first L.extent elements and do not overlap;
+// alt_* are scratch arrays of L.extent elements.
 template <typename K, class Digit, int BITS>
 rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, const void *keys_in,
                         void *keys_out, const uint32_t *vals_in, uint32_t *vals_out, void *alt_keys,
-                        uint32_t *alt_vals, const uint64_t *seg_off, char *base, hipStream_t stream) {
+                        uint32_t *alt_vals, const uint64_t *seg_lo, const uint64_t *seg_hi, char *base,
+                        hipStream_t stream) {
   const bool pairs = vals_in != nullptr;
   const uint32_t P = L.npasses;
   constexpr int KPT = sizeof(K) >= 16 ? 8 : 16;
@@ -38,10 +40,10 @@ rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, 
   uint32_t *sums = (uint32_t *)(base + L.off_sums);
   rs_status st;
 
-  SegPlanParams q{seg_off, L.nseg, L.small_max, L.tile, nlarge, large_ids, tile_base, nsmall, small_ids};
+  SegPlanParams q{seg_lo, seg_hi, L.nseg, L.small_max, L.tile, nlarge, large_ids, tile_base, nsmall, small_ids};
   RS_TIMED("rs_seg_plan", stream, hipLaunchKernelGGL((rs_seg_plan<1024>), dim3(1), dim3(1024), 0, stream, q));
   if ((st = check_launch("rs_seg_plan")) != RS_OK) return st;
-  SegTilesParams tq{seg_off, large_ids, tile_base, nlarge, L.tile, tiles, ntotal};
+  SegTilesParams tq{seg_lo, seg_hi, large_ids, tile_base, nlarge, L.tile, tiles, ntotal};
   RS_TIMED("rs_seg_tiles", stream,
            hipLaunchKernelGGL(rs_seg_tiles, dim3((uint32_t)((L.tiles_bound + 255) / 256)), dim3(256), 0, stream, tq));
   if ((st = check_launch("rs_seg_tiles")) != RS_OK) return st;
@@ -54,7 +56,8 @@ rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, 
     sp.pass_cells[i] = p.pass_cells[i];
   }
   sp.npasses = P;
-  sp.seg_off = seg_off;
+  sp.seg_lo = seg_lo;
+  sp.seg_hi = seg_hi;
   sp.small_ids = small_ids;
   sp.nsmall = nsmall;
   if (pairs)
@@ -70,7 +73,7 @@ rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, 
   // large arrays: the passes, every array sharing each launch
   return with_block<K, BITS>(L.block, [&]<int BLOCK>() {
     return prescanned_passes<K, Digit, BITS, BLOCK, true>(p, digits, P, keys_in, keys_out, vals_in, vals_out,
-                                                          alt_keys, alt_vals, L.total, L.tiles_bound, table, sums,
+                                                          alt_keys, alt_vals, L.extent, L.tiles_bound, table, sums,
                                                           tiles, ntotal, stream);
   });
 }

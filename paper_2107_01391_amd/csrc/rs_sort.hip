@@ -67,6 +67,18 @@ rs_status launch_fill(void *p, size_t bytes, uint32_t value, hipStream_t stream)
   return check_launch("rs_fill");
 }
 
+rs_status launch_copy(void *dst, const void *src, size_t bytes, hipStream_t stream) {
+  if (bytes == 0) return RS_OK;
+  const uint64_t n4 = bytes / 4;
+  uint64_t blocks = (n4 + 255) / 256;
+  const uint64_t cap = (uint64_t)cu_count() * 8;
+  if (blocks > cap) blocks = cap;
+  RS_TIMED("rs_copy", stream,
+           hipLaunchKernelGGL(rs_copy, dim3((uint32_t)blocks), dim3(256), 0, stream, (uint32_t *)dst,
+                              (const uint32_t *)src, n4));
+  return check_launch("rs_copy");
+}
+
 // --------------------------------------------------------- grouped passes
 
 template <typename K, class Digit, int BITS>
@@ -125,13 +137,11 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   const bool odd = pl.npasses % 2 == 1;
   if (odd && keys_in == keys_out) {
     // pass 0 would read and write X: start from a copy in Y
-    if (hipMemcpyAsync(Y, keys_in, pl.n * kb, hipMemcpyDeviceToDevice, stream) != hipSuccess)
-      return fail(RS_ERR_HIP, "hipMemcpyAsync");
+    if ((st = launch_copy(Y, keys_in, pl.n * kb, stream)) != RS_OK) return st;
     src = Y;
   }
   if (pl.pairs && odd && vals_in == vals_out) {
-    if (hipMemcpyAsync(YV, vals_in, pl.n * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
-      return fail(RS_ERR_HIP, "hipMemcpyAsync");
+    if ((st = launch_copy(YV, vals_in, pl.n * 4, stream)) != RS_OK) return st;
     srcv = YV;
   }
   for (uint32_t i = 0; i < pl.npasses; ++i) {

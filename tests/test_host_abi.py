@@ -122,3 +122,63 @@ def test_codec_host_build(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "codec ok" in r.stdout
+
+
+# ------------------------------------------------------------ tuning table
+
+def test_tuning_defaults_set_get_clear_and_file(tmp_path):
+    d = B.key_desc("u32", base=256, ndims=4)
+    B.rs_tuning_clear()
+    t = B.rs_tuning_get(d, 1 << 20, True)
+    assert t.tile_block in (256, 512) and 4 <= t.digit_bits <= 11
+    mine = B.Tuning(4, 100, 256, 0, 12345)
+    B.rs_tuning_set(d, 1 << 20, True, False, mine)
+    got = B.rs_tuning_get(d, (1 << 21) - 1, True)  # same size class
+    assert got.as_dict() == mine.as_dict()
+    other = B.rs_tuning_get(d, 1 << 21, True)  # next class: defaults
+    assert other.as_dict() == t.as_dict()
+    assert B.rs_tuning_get(d, 1 << 20, False).as_dict() == t.as_dict()  # keys only: its own entry
+    path = str(tmp_path / "tuning.txt")
+    B.rs_tuning_save(path)
+    B.rs_tuning_clear()
+    assert B.rs_tuning_get(d, 1 << 20, True).as_dict() == t.as_dict()
+    B.rs_tuning_load(path)
+    assert B.rs_tuning_get(d, 1 << 20, True).as_dict() == mine.as_dict()
+    B.rs_tuning_clear()
+
+
+def test_tuning_rejects_bad_fields_and_files(tmp_path):
+    d = B.key_desc("u32")
+    for bad in (B.Tuning(3, 1024, 256, 0, 1), B.Tuning(8, 1, 256, 0, 1), B.Tuning(8, 1024, 300, 0, 1)):
+        with pytest.raises(B.RSError) as e:
+            B.rs_tuning_set(d, 1000, True, False, bad)
+        assert e.value.status == 2
+    p = tmp_path / "bad.txt"
+    p.write_text("1 2 3\n")
+    with pytest.raises(B.RSError):
+        B.rs_tuning_load(str(p))
+
+
+def test_tuned_choice_changes_the_plan_not_the_contract():
+    """A kept choice reaches the planner: 4-bit passes need another tmp size."""
+    d = B.key_desc("u32", base=2, ndims=32)
+    B.rs_tuning_clear()
+    n = 1 << 22
+    default = B.rs_temp_bytes(d, n, True)
+    B.rs_tuning_set(d, n, True, False, B.Tuning(4, 1024, 256, 0, 1 << 40))  # chained, 8 passes of 16 cells
+    chained = B.rs_temp_bytes(d, n, True)
+    B.rs_tuning_clear()
+    assert chained != default
+    assert B.rs_tune_temp_bytes(d, n, 0, True) >= max(chained, default)
+    assert B.rs_tune_temp_bytes(d, n, 16, True) >= B.rs_batched_temp_bytes(d, n, 16, True)
+
+
+def test_graph_capture_refuses_validation_and_null_out():
+    d = B.key_desc("u32", validate=True)
+    lib = B.load_library()
+    h = ctypes.c_void_p(None)
+    fake = ctypes.c_void_p(256)
+    assert lib.rs_graph_sort(ctypes.byref(d), fake, fake, fake, fake, 10, fake, 1 << 20, ctypes.byref(h)) == 5
+    assert h.value is None
+    assert lib.rs_graph_sort(ctypes.byref(d), fake, fake, fake, fake, 10, fake, 1 << 20, None) == 1
+    assert lib.rs_graph_destroy(None) == 0
