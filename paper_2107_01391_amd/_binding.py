@@ -26,7 +26,12 @@ EXPORTED = ["rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_batched_temp_b
             "rs_status_string", "rs_last_error", "rs_prof_enable", "rs_prof_query",
             "rs_tuning_get", "rs_tuning_set", "rs_tuning_clear", "rs_tune_temp_bytes", "rs_tune_sort",
             "rs_tune_batched", "rs_tuning_save", "rs_tuning_load",
-            "rs_graph_sort", "rs_graph_sort_batched", "rs_graph_launch", "rs_graph_destroy"]
+            "rs_graph_sort", "rs_graph_sort_batched", "rs_graph_launch", "rs_graph_destroy",
+            "rs_server_work_bytes", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
+            "rs_server_result", "rs_server_release", "rs_server_get_stats", "rs_server_reset_stats",
+            "rs_server_clock", "rs_server_destroy"]
+RS_ERR_BUSY = 8
+RS_SERVE_BATCHED, RS_SERVE_PER_REQUEST = 0, 1
 
 
 class RSError(RuntimeError):
@@ -55,6 +60,21 @@ class Tuning(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("capacity", ctypes.c_uint64), ("max_slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("streams", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("with_values", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("keys_sorted", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("busy", ctypes.c_uint64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("span_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 _lib = None
@@ -106,6 +126,23 @@ def load_library(path: str | None = None):
     for f in ("rs_tuning_get", "rs_tuning_set", "rs_tuning_clear", "rs_tune_temp_bytes", "rs_tune_sort",
               "rs_tune_batched", "rs_tuning_save", "rs_tuning_load", "rs_graph_sort", "rs_graph_sort_batched",
               "rs_graph_launch", "rs_graph_destroy"):
+        getattr(lib, f).restype = ctypes.c_int
+    cp = ctypes.POINTER(ServerConfig)
+    u64p = ctypes.POINTER(u64)
+    lib.rs_server_work_bytes.argtypes = [dp, cp, ctypes.POINTER(sz)]
+    lib.rs_server_create.argtypes = [dp, cp, vp, vp, vp, vp, vp, sz, gp]
+    lib.rs_server_submit.argtypes = [vp, vp, vp, u64, u64, u64p]
+    lib.rs_server_poll.argtypes = [vp, u64, ctypes.POINTER(ci)]
+    lib.rs_server_wait.argtypes = [vp, u64]
+    lib.rs_server_result.argtypes = [vp, u64, u64p, u64p]
+    lib.rs_server_release.argtypes = [vp, u64]
+    lib.rs_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.rs_server_reset_stats.argtypes = [vp]
+    lib.rs_server_clock.argtypes = [u64p]
+    lib.rs_server_destroy.argtypes = [vp]
+    for f in ("rs_server_work_bytes", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
+              "rs_server_result", "rs_server_release", "rs_server_get_stats", "rs_server_reset_stats",
+              "rs_server_clock", "rs_server_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib

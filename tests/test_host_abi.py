@@ -182,3 +182,48 @@ def test_graph_capture_refuses_validation_and_null_out():
     assert h.value is None
     assert lib.rs_graph_sort(ctypes.byref(d), fake, fake, fake, fake, 10, fake, 1 << 20, None) == 1
     assert lib.rs_graph_destroy(None) == 0
+
+
+# ------------------------------------------------------------------ server
+
+def _cfg(**kw):
+    c = dict(capacity=1 << 20, max_slots=64, max_batch=0, streams=2, mode=0, with_values=1, reserved=0)
+    c.update(kw)
+    return B.ServerConfig(*c.values())
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(capacity=0), 2), (dict(capacity=(1 << 32) + 1), 2), (dict(max_slots=0), 2),
+    (dict(streams=0), 2), (dict(streams=9), 2), (dict(mode=7), 2)])
+def test_server_config_rejected(kw, status):
+    d = B.key_desc("u32")
+    lib = B.load_library()
+    need = ctypes.c_size_t(0)
+    assert lib.rs_server_work_bytes(ctypes.byref(d), ctypes.byref(_cfg(**kw)), ctypes.byref(need)) == status
+    assert B.rs_last_error()
+
+
+def test_server_work_bytes_and_create_checks_before_any_device_call():
+    d = B.key_desc("u32")
+    lib = B.load_library()
+    need = ctypes.c_size_t(0)
+    assert lib.rs_server_work_bytes(ctypes.byref(d), ctypes.byref(_cfg()), ctypes.byref(need)) == 0
+    one = ctypes.c_size_t(0)
+    assert lib.rs_server_work_bytes(ctypes.byref(d), ctypes.byref(_cfg(streams=1)), ctypes.byref(one)) == 0
+    assert need.value >= 2 * one.value - 256 and one.value > 0
+    per = ctypes.c_size_t(0)
+    assert lib.rs_server_work_bytes(ctypes.byref(d), ctypes.byref(_cfg(mode=1)), ctypes.byref(per)) == 0
+    h = ctypes.c_void_p(None)
+    fake = ctypes.c_void_p(1 << 20)
+    # missing arenas, then work too small, then validation refused: all before any HIP call
+    assert lib.rs_server_create(ctypes.byref(d), ctypes.byref(_cfg()), None, None, None, None, fake, need.value,
+                                ctypes.byref(h)) == 1
+    assert lib.rs_server_create(ctypes.byref(d), ctypes.byref(_cfg()), fake, fake, fake, fake, fake, need.value - 1,
+                                ctypes.byref(h)) == 4
+    dv = B.key_desc("u32", validate=True)
+    assert lib.rs_server_create(ctypes.byref(dv), ctypes.byref(_cfg()), fake, fake, fake, fake, fake, need.value,
+                                ctypes.byref(h)) == 5
+    assert h.value is None
+    assert lib.rs_server_destroy(None) == 0
+    t = ctypes.c_uint64(0)
+    assert lib.rs_server_clock(ctypes.byref(t)) == 0 and t.value > 0
