@@ -10,9 +10,11 @@ Prints one JSON line: the whole-sort rate in Gkeys/s, the dominant kernel's
 (rs_rank_scatter) achieved bandwidth against the 8 TB/s HBM peak, measured
 live with HIP events on the launch stream over the timed steps, the CPU
 oracle timed on a bounded sample on this host, and the batched form against
-one call per array on 4096 arrays of log-uniform size in [2^10, 2^22].
+one call per array on 4096 arrays of log-uniform size in [2^10, 2^22], and
+the served loop (continuous batching vs one launch per request) on a
+seeded Poisson trace at equal p99 latency.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-batched]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-batched] [--no-served]
 """
 from __future__ import annotations
 
@@ -185,6 +187,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-arrays", type=int, default=4096)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (scale reference for PMC byte counters)")
     args = ap.parse_args()
@@ -271,6 +275,17 @@ def main() -> int:
     if not args.no_batched:
         print("[bench] batched vs per-array", file=sys.stderr, flush=True)
         batched = batched_vs_per_array(torch, B, workloads, args.batched_arrays)
+        torch.cuda.empty_cache()
+
+    served = None
+    if not args.no_served:
+        from paper_2107_01391_amd import serve
+        print("[bench] served: per-request vs batched", file=sys.stderr, flush=True)
+        rows = serve.sweep([2000.0, 8000.0, 32000.0, 0.0], args.served_requests, 50, 1 << 28, 4, verbose=False)
+        served = {"trace": f"{args.served_requests} requests after 50 warm-up, sizes log-uniform [2^10, 2^22], "
+                           "Poisson arrivals (rate 0 = closed loop), arena 2^28 keys, 4 streams",
+                  "rows": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for r in rows],
+                  "equal_p99": serve.gate(rows)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -286,7 +301,7 @@ def main() -> int:
                                "base 256, 4 dimensions, stable ascending (rs_sort_pairs)",
                    "n": n, "passes": passes},
         "roofline": roofline, "whole_sort": whole, "cpu_baseline": cpu, "batched_vs_per_array": batched,
-        "output_check": ok,
+        "served": served, "output_check": ok,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)

@@ -19,7 +19,10 @@
  * launch streams is idle:
  *   - RS_SERVE_BATCHED: every queued request (up to max_batch) in one
  *     segmented launch sequence, the rs_sort_batched kernels over
- *     begin/end ranges of the arena.
+ *     begin/end ranges of the arena.  Fewer than min_batch queued requests
+ *     run as single-array sorts instead, so light load costs what the
+ *     baseline does; the segmented sequence pays off once enough requests
+ *     share it.
  *   - RS_SERVE_PER_REQUEST: one rs_sort_pairs / rs_sort_keys launch per
  *     request (the baseline).
  *   - With streams > 1, launches overlap on the device.
@@ -58,7 +61,8 @@ typedef struct rs_server_config {
   uint32_t streams;      /* launches in flight at once, 1..8 */
   uint32_t mode;         /* RS_SERVE_BATCHED or RS_SERVE_PER_REQUEST */
   uint32_t with_values;  /* requests carry uint32 values */
-  uint32_t reserved;     /* 0 */
+  uint32_t min_batch;    /* batched mode: fewer queued requests than this run as single-array sorts
+                            in one launch slot (0 = 4) */
 } rs_server_config;
 
 typedef struct rs_server_stats {
@@ -81,10 +85,10 @@ rs_status rs_server_work_bytes(const rs_key_desc *desc, const rs_server_config *
 rs_status rs_server_create(const rs_key_desc *desc, const rs_server_config *cfg, void *keys_in, void *keys_out,
                            uint32_t *vals_in, uint32_t *vals_out, void *work, size_t work_bytes, rs_server **out);
 
-/* Submits a request of n keys (and values when the server carries them):
- * host or device pointers, copied before the call returns for host memory
- * and in stream order for device memory (do not reuse them before the
- * request is done).  arrival_ns: the request's arrival on rs_server_clock
+/* Submits a request of n keys (and values when the server carries them).
+ * keys / vals are host or device pointers; the copy into the arena is
+ * enqueued on the server's upload stream, so they must stay unchanged until
+ * the request is done.  arrival_ns: the request's arrival on rs_server_clock
  * (0 = now).  RS_ERR_BUSY: not admitted now, nothing kept. */
 rs_status rs_server_submit(rs_server *s, const void *keys, const uint32_t *vals, uint64_t n, uint64_t arrival_ns,
                            uint64_t *ticket);
@@ -95,6 +99,11 @@ rs_status rs_server_poll(rs_server *s, uint64_t ticket, int *done);
 
 /* Blocks until the request is done; returns its status. */
 rs_status rs_server_wait(rs_server *s, uint64_t ticket);
+
+/* Moves up to `max` tickets of requests that finished since the last
+ * collect (sorted or failed) into tickets[], in completion order, and sets
+ * *count.  With wait_us > 0 and none ready, waits up to that long for one. */
+rs_status rs_server_collect(rs_server *s, uint64_t *tickets, uint32_t max, uint32_t *count, uint32_t wait_us);
 
 /* Where a done request's result lies: keys_out[*offset, *offset + *n) and
  * the same range of vals_out. */

@@ -29,7 +29,7 @@ EXPORTED = ["rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_batched_temp_b
             "rs_graph_sort", "rs_graph_sort_batched", "rs_graph_launch", "rs_graph_destroy",
             "rs_server_work_bytes", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
             "rs_server_result", "rs_server_release", "rs_server_get_stats", "rs_server_reset_stats",
-            "rs_server_clock", "rs_server_destroy"]
+            "rs_server_clock", "rs_server_destroy", "rs_server_collect"]
 RS_ERR_BUSY = 8
 RS_SERVE_BATCHED, RS_SERVE_PER_REQUEST = 0, 1
 
@@ -65,7 +65,7 @@ class Tuning(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_uint64), ("max_slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
                 ("streams", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("with_values", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("min_batch", ctypes.c_uint32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -140,9 +140,10 @@ def load_library(path: str | None = None):
     lib.rs_server_reset_stats.argtypes = [vp]
     lib.rs_server_clock.argtypes = [u64p]
     lib.rs_server_destroy.argtypes = [vp]
+    lib.rs_server_collect.argtypes = [vp, u64p, u32, ctypes.POINTER(u32), u32]
     for f in ("rs_server_work_bytes", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
               "rs_server_result", "rs_server_release", "rs_server_get_stats", "rs_server_reset_stats",
-              "rs_server_clock", "rs_server_destroy"):
+              "rs_server_clock", "rs_server_destroy", "rs_server_collect"):
         getattr(lib, f).restype = ctypes.c_int
     if path is None:
         _lib = lib

@@ -55,6 +55,7 @@ struct SegLayout {
   uint64_t tiles_bound = 0;  // large-array tiles, at most
   uint32_t small_grid = 1;
   bool own_alt = false;
+  bool any_large = true;  // false when the caller knows every array is small: no passes are launched
   size_t off_alt_keys = 0, off_alt_vals = 0;
   size_t off_ctrl = 0;  // nlarge, nsmall, tiles in use
   size_t off_large_ids = 0, off_tile_base = 0, off_small_ids = 0;

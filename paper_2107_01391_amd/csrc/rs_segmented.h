@@ -43,10 +43,13 @@ rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, 
   SegPlanParams q{seg_lo, seg_hi, L.nseg, L.small_max, L.tile, nlarge, large_ids, tile_base, nsmall, small_ids};
   RS_TIMED("rs_seg_plan", stream, hipLaunchKernelGGL((rs_seg_plan<1024>), dim3(1), dim3(1024), 0, stream, q));
   if ((st = check_launch("rs_seg_plan")) != RS_OK) return st;
-  SegTilesParams tq{seg_lo, seg_hi, large_ids, tile_base, nlarge, L.tile, tiles, ntotal};
-  RS_TIMED("rs_seg_tiles", stream,
-           hipLaunchKernelGGL(rs_seg_tiles, dim3((uint32_t)((L.tiles_bound + 255) / 256)), dim3(256), 0, stream, tq));
-  if ((st = check_launch("rs_seg_tiles")) != RS_OK) return st;
+  if (L.any_large) {
+    SegTilesParams tq{seg_lo, seg_hi, large_ids, tile_base, nlarge, L.tile, tiles, ntotal};
+    RS_TIMED("rs_seg_tiles", stream,
+             hipLaunchKernelGGL(rs_seg_tiles, dim3((uint32_t)((L.tiles_bound + 255) / 256)), dim3(256), 0, stream,
+                                tq));
+    if ((st = check_launch("rs_seg_tiles")) != RS_OK) return st;
+  }
 
   // small arrays: straight from the input to the output
   SmallParams<Digit> sp;
@@ -71,6 +74,7 @@ rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, 
   if ((st = check_launch("rs_small_sort")) != RS_OK) return st;
 
   // large arrays: the passes, every array sharing each launch
+  if (!L.any_large) return RS_OK;
   return with_block<K, BITS>(L.block, [&]<int BLOCK>() {
     return prescanned_passes<K, Digit, BITS, BLOCK, true>(p, digits, P, keys_in, keys_out, vals_in, vals_out,
                                                           alt_keys, alt_vals, L.extent, L.tiles_bound, table, sums,

@@ -50,6 +50,10 @@ struct Launch {
   std::vector<uint64_t> tickets;
 };
 
+struct Span {
+  uint64_t offset, n;
+};
+
 // Scratch of one launch stream inside `work`.
 struct StreamWork {
   size_t tmp_off = 0, tmp_bytes = 0, lo_off = 0, hi_off = 0;
@@ -86,15 +90,15 @@ rs_status layout_of(const rs_key_desc *desc, const rs_server_config *c, Layout *
     st = make_batched(desc, c->capacity, c->capacity, batch_cap(c), pairs, &p, &why);
     if (st != RS_OK) return fail(st, why);
     tmp = p.total;
-  } else {
-    // the largest single request, and the largest chained one (its look-back
-    // words grow with n)
-    const uint64_t sizes[2] = {c->capacity, std::min<uint64_t>(c->capacity, 3ull << 20)};
-    for (uint64_t n : sizes) {
-      size_t b = 0;
-      if ((st = rs_temp_bytes(desc, n, pairs, &b)) != RS_OK) return st;
-      tmp = std::max(tmp, b);
-    }
+  }
+  // a lone request runs the single-array sort (in both modes): the largest
+  // request, and the largest chained one (its look-back words grow with n)
+  const uint64_t sizes[2] = {std::min<uint64_t>(c->capacity, RS_MAX_ELEMENTS),
+                             std::min<uint64_t>(c->capacity, 3ull << 20)};
+  for (uint64_t n : sizes) {
+    size_t b = 0;
+    if ((st = rs_temp_bytes(desc, n, pairs, &b)) != RS_OK) return st;
+    tmp = std::max(tmp, b);
   }
   L->tmp_bytes = align256(tmp);
   L->per.resize(c->streams);
@@ -143,6 +147,7 @@ struct rs_server {
   std::unordered_map<uint64_t, Request> reqs;
   std::deque<uint64_t> queue;
   std::deque<Launch> inflight;
+  std::deque<uint64_t> done_q;  // done, not yet collected
   uint64_t next_ticket = 1;
   uint32_t slots_used = 0;
 
@@ -197,6 +202,7 @@ struct rs_server {
     r.state = kDone;
     r.status = st;
     r.done_at = when;
+    done_q.push_back(t);
     if (st == RS_OK) {
       lat_ms.push_back((double)(when - std::min(when, r.arrival)) / 1e6);
       keys_sorted += r.n;
@@ -205,17 +211,19 @@ struct rs_server {
     }
   }
 
-  // Enqueues one launch on stream i for the given requests (lock held).
-  rs_status launch(uint32_t i, const std::vector<uint64_t> &tickets, hipEvent_t uploaded) {
+  // Enqueues one launch on stream i for the given requests.  Runs without
+  // the lock: it touches only stream i's resources and the spans given.
+  rs_status launch(uint32_t i, const std::vector<Span> &spans, hipEvent_t uploaded) {
     hipStream_t s = streams[i];
     if (hipStreamWaitEvent(s, uploaded, 0) != hipSuccess) return fail(RS_ERR_HIP, "hipStreamWaitEvent");
     const StreamWork &w = lay.per[i];
     void *tmp = work + w.tmp_off;
     const bool pairs = cfg.with_values != 0;
     const size_t kb = key_plan.key.key_bytes;
-    if (cfg.mode == RS_SERVE_PER_REQUEST) {
-      for (uint64_t t : tickets) {
-        const Request &r = reqs[t];
+    const uint32_t min_batch = cfg.min_batch ? cfg.min_batch : 4;
+    if (cfg.mode == RS_SERVE_PER_REQUEST || spans.size() < min_batch) {
+      // one launch sequence per request: the baseline, and small batches
+      for (const Span &r : spans) {
         const size_t o = (size_t)r.offset;
         rs_status st = pairs ? rs_sort_pairs(&desc, kin + o * kb, kout + o * kb, vin + o, vout + o, r.n, tmp,
                                              w.tmp_bytes, s)
@@ -224,25 +232,31 @@ struct rs_server {
       }
       return RS_OK;
     }
-    // batched: one segmented sequence over [lo, hi) ranges of the arena
+    // batched: one segmented sequence over [lo, hi) ranges of the arena;
+    // the host knows the sizes, so the tile bound counts only the arrays
+    // too large to sort on chip, and an all-small batch launches no pass
+    Plan p;
+    std::string why;
+    rs_status st = make_batched(&desc, 1, cfg.capacity, (uint32_t)spans.size(), pairs, &p, &why);
+    if (st != RS_OK) return fail(st, why);
     uint64_t *lo = staging[i], *hi = staging[i] + batch_cap(&cfg);
-    uint64_t total = 0;
-    for (size_t j = 0; j < tickets.size(); ++j) {
-      const Request &r = reqs[tickets[j]];
-      lo[j] = r.offset;
-      hi[j] = r.offset + r.n;
-      total += r.n;
+    uint64_t large = 0;
+    for (size_t j = 0; j < spans.size(); ++j) {
+      lo[j] = spans[j].offset;
+      hi[j] = spans[j].offset + spans[j].n;
+      if (spans[j].n > p.seg.small_max) large += spans[j].n;
     }
-    const size_t nb = tickets.size() * 8;
+    if (large > 1) {
+      st = make_batched(&desc, large, cfg.capacity, (uint32_t)spans.size(), pairs, &p, &why);
+      if (st != RS_OK) return fail(st, why);
+    }
+    p.seg.any_large = large > 0;
+    if (p.total > w.tmp_bytes) return fail(RS_ERR_TMP_TOO_SMALL, "server scratch below this batch's plan");
+    const size_t nb = spans.size() * 8;
     uint64_t *dlo = (uint64_t *)(work + w.lo_off), *dhi = (uint64_t *)(work + w.hi_off);
     if (hipMemcpyAsync(dlo, lo, nb, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(dhi, hi, nb, hipMemcpyHostToDevice, s) != hipSuccess)
       return fail(RS_ERR_HIP, "hipMemcpyAsync of array bounds");
-    Plan p;
-    std::string why;
-    rs_status st = make_batched(&desc, total, cfg.capacity, (uint32_t)tickets.size(), pairs, &p, &why);
-    if (st != RS_OK) return fail(st, why);
-    if (p.total > w.tmp_bytes) return fail(RS_ERR_TMP_TOO_SMALL, "server scratch below this batch's plan");
     return batched_run(p, kin, kout, pairs ? vin : nullptr, pairs ? vout : nullptr, dlo, dhi, tmp, s);
   }
 
@@ -259,25 +273,33 @@ struct rs_server {
       const uint32_t i = (uint32_t)(std::find(stream_busy.begin(), stream_busy.end(), false) - stream_busy.begin());
       const uint32_t take = cfg.mode == RS_SERVE_PER_REQUEST ? 1u : batch_cap(&cfg);
       std::vector<uint64_t> tickets;
+      std::vector<Span> spans;
       while (!queue.empty() && tickets.size() < take) {
-        tickets.push_back(queue.front());
+        const uint64_t t = queue.front();
         queue.pop_front();
+        Request &r = reqs[t];
+        r.state = kRunning;
+        tickets.push_back(t);
+        spans.push_back(Span{r.offset, r.n});
       }
+      stream_busy[i] = true;
       hipEvent_t uploaded = take_event(), done = take_event();
+      lk.unlock();
+      // every request taken was uploaded (in stream order) before it was queued
       rs_status st = (uploaded && done) ? RS_OK : fail(RS_ERR_HIP, "hipEventCreate");
       if (st == RS_OK && hipEventRecord(uploaded, upload) != hipSuccess) st = fail(RS_ERR_HIP, "hipEventRecord");
-      if (st == RS_OK) st = launch(i, tickets, uploaded);
+      if (st == RS_OK) st = launch(i, spans, uploaded);
       if (st == RS_OK && hipEventRecord(done, streams[i]) != hipSuccess) st = fail(RS_ERR_HIP, "hipEventRecord");
-      if (uploaded) event_pool.push_back(uploaded);  // reusable once recorded again later: waits are enqueued
+      lk.lock();
+      if (uploaded) event_pool.push_back(uploaded);  // the wait is enqueued: the event may be recorded again
       if (st != RS_OK) {
         const uint64_t t_now = now_ns();
         for (uint64_t t : tickets) finish(t, st, t_now);
         if (done) event_pool.push_back(done);
+        stream_busy[i] = false;
         cv_done.notify_all();
         continue;
       }
-      for (uint64_t t : tickets) reqs[t].state = kRunning;
-      stream_busy[i] = true;
       ++launches;
       inflight.push_back(Launch{i, done, std::move(tickets)});
       cv_complete.notify_one();
@@ -408,6 +430,7 @@ rs_status rs_server_submit(rs_server *s, const void *keys, const uint32_t *vals,
     r.state = kDone;
     r.done_at = arrival;
     s->reqs[t] = r;
+    s->done_q.push_back(t);
     *ticket = t;
     return RS_OK;
   }
@@ -451,6 +474,22 @@ rs_status rs_server_wait(rs_server *s, uint64_t ticket) {
   auto j = s->reqs.find(ticket);
   if (j == s->reqs.end()) return fail(RS_ERR_BAD_DESC, "ticket released while waiting");
   return j->second.status == RS_OK ? RS_OK : fail(j->second.status, "request failed");
+}
+
+rs_status rs_server_collect(rs_server *s, uint64_t *tickets, uint32_t max, uint32_t *count, uint32_t wait_us) {
+  g_last_error.clear();
+  if (!s || !count || (max && !tickets)) return fail(RS_ERR_NULL_ARG, "server, tickets and count are required");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (wait_us && s->done_q.empty())
+    s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), [&] { return !s->done_q.empty(); });
+  uint32_t k = 0;
+  while (k < max && !s->done_q.empty()) {
+    const uint64_t t = s->done_q.front();
+    s->done_q.pop_front();
+    if (s->reqs.count(t)) tickets[k++] = t;  // skip tickets already released
+  }
+  *count = k;
+  return RS_OK;
 }
 
 rs_status rs_server_result(rs_server *s, uint64_t ticket, uint64_t *offset, uint64_t *n) {

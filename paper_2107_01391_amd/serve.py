@@ -23,11 +23,12 @@ from . import _binding as B
 
 class Server:
     def __init__(self, desc: B.KeyDesc, capacity: int, max_slots: int = 256, streams: int = 2,
-                 mode: int = B.RS_SERVE_BATCHED, with_values: bool = True, max_batch: int = 0):
+                 mode: int = B.RS_SERVE_BATCHED, with_values: bool = True, max_batch: int = 0,
+                 min_batch: int = 0):
         import torch
         B.load_library()
         self.desc = desc
-        self.cfg = B.ServerConfig(capacity, max_slots, max_batch, streams, mode, int(bool(with_values)), 0)
+        self.cfg = B.ServerConfig(capacity, max_slots, max_batch, streams, mode, int(bool(with_values)), min_batch)
         kb = {0: 4, 1: 8, 2: 8, 3: 16}[desc.kind]
         self.kb = kb
         dev = "cuda"
@@ -73,6 +74,13 @@ class Server:
     def wait(self, ticket: int) -> None:
         B._check(B.load_library().rs_server_wait(self._h, ticket))
 
+    def collect(self, wait_us: int = 0, max_n: int = 1024) -> list[int]:
+        """Tickets finished since the last collect (waits up to wait_us for one)."""
+        buf = (ctypes.c_uint64 * max_n)()
+        k = ctypes.c_uint32(0)
+        B._check(B.load_library().rs_server_collect(self._h, buf, max_n, ctypes.byref(k), wait_us))
+        return list(buf[:k.value])
+
     def result(self, ticket: int):
         """(keys bytes, values) views of the output arena for a done request."""
         off, n = ctypes.c_uint64(0), ctypes.c_uint64(0)
@@ -107,7 +115,8 @@ class Server:
 
 def make_pool(count: int, sizes: np.ndarray, seed: int):
     """`count` distinct device request arrays (u32 keys, local-index values)
-    whose sizes cycle through `sizes`; drawn on the device, seeded."""
+    whose sizes cycle through `sizes`; drawn on the device, seeded.  A trace
+    request takes the first sizes[i] keys of its pool entry."""
     import torch
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
@@ -124,56 +133,67 @@ def make_pool(count: int, sizes: np.ndarray, seed: int):
 def run_trace(server: Server, pool, gaps_s: np.ndarray, sizes: np.ndarray, warmup: int = 0) -> dict:
     """Submits request i (pool entry i mod len(pool), its first sizes[i]
     keys) at arrival time sum(gaps[:i+1]); all-zero gaps submit as fast as
-    admission allows.  A refused (busy) request is retried after the oldest
-    outstanding one completes; its latency still counts from its arrival.
-    Done requests are released as soon as they are seen.  Statistics cover
-    the requests after the first `warmup`."""
+    admission allows.  A refused (busy) request is retried once another one
+    completes; its latency still counts from its arrival.  Finished requests
+    are collected and released as they complete.  Statistics cover the
+    requests after the first `warmup`."""
     count = len(gaps_s)
     t0 = Server.clock()
     arrivals = t0 + np.cumsum(gaps_s * 1e9).astype(np.int64)
-    pending: list[int] = []
+    outstanding = 0
     i = 0
-    while i < count or pending:
-        if pending:
-            still = []
-            for t in pending:
-                if server.done(t):
-                    server.release(t)
-                else:
-                    still.append(t)
-            pending = still
+
+    def reap(wait_us):
+        nonlocal outstanding
+        got = server.collect(wait_us)
+        for t in got:
+            server.release(t)
+        outstanding -= len(got)
+        return len(got)
+
+    while i < count or outstanding:
+        if outstanding:
+            reap(0)
         if i < count and Server.clock() >= arrivals[i]:
             k, v = pool[i % len(pool)]
             n = int(min(sizes[i], k.numel()))
             t = server.submit(k, v, n, int(arrivals[i]))
             if t is None:
-                if not pending:
+                if not outstanding:
                     raise RuntimeError("request refused with nothing outstanding: arena or slots too small")
-                server.wait(pending[0])
+                reap(2000)
                 continue
-            pending.append(t)
+            outstanding += 1
             i += 1
             if i == warmup:
-                for t in pending:
-                    server.wait(t)
-                    server.release(t)
-                pending = []
+                while outstanding:
+                    reap(2000)
                 server.reset_stats()
             continue
-        wait_s = 20e-6 if i >= count else min(20e-6, max(0.0, (arrivals[i] - Server.clock()) / 1e9))
-        if wait_s > 0:
-            time.sleep(wait_s)
+        if i >= count:
+            reap(500)
+        else:
+            left_us = int((arrivals[i] - Server.clock()) / 1e3)
+            if left_us > 0:
+                if outstanding:
+                    reap(min(left_us, 500))
+                else:
+                    time.sleep(min(left_us, 500) / 1e6)
     st = server.stats()
     st["gkeys_per_s"] = st["keys_sorted"] / (st["span_ms"] / 1e3) / 1e9 if st["span_ms"] > 0 else 0.0
     return st
 
 
-def sweep(rates, requests: int, warmup: int, capacity: int, streams: int, seed: int = 20210708) -> list[dict]:
+def sweep(rates, requests: int, warmup: int, capacity: int, streams: int, seed: int = 20210708,
+          verbose: bool = True) -> list[dict]:
+    """The same seeded traces (sizes log-uniform in [2^10, 2^22], Poisson
+    arrivals at each rate; rate 0 = as fast as admission allows) through a
+    per-request server and a batched server."""
     from . import workloads
     desc = B.key_desc("u32", base=256, ndims=4)
     rows = []
     sizes_all = workloads.batched_sizes(requests + warmup, seed_extra=[seed])
-    pool = make_pool(64, sizes_all[:64], seed)
+    pool = make_pool(32, np.array([int(sizes_all.max())]), seed)  # entries long enough for every size
     for mode, name in ((B.RS_SERVE_PER_REQUEST, "per_request"), (B.RS_SERVE_BATCHED, "batched")):
         srv = Server(desc, capacity, max_slots=512, streams=streams, mode=mode)
         try:
@@ -183,21 +203,50 @@ def sweep(rates, requests: int, warmup: int, capacity: int, streams: int, seed: 
                 st = run_trace(srv, pool, gaps, sizes_all, warmup=warmup)
                 st.update({"mode": name, "rate": rate})
                 rows.append(st)
-                print(json.dumps(st), flush=True)
+                if verbose:
+                    print(json.dumps(st), flush=True)
         finally:
             srv.close()
     return rows
 
 
+def gate(rows: list[dict], ref_rate: float = 2000.0) -> dict:
+    """Throughput at equal p99 latency.  Each per-request rate's p99 is a
+    latency bound; within it, the best throughput each server reached over
+    the sweep is compared.  `at_ref` is the bound set by the per-request
+    server at ref_rate."""
+    per = [r for r in rows if r["mode"] == "per_request"]
+    bat = [r for r in rows if r["mode"] == "batched"]
+
+    def best(rs, bound):
+        ok = [r for r in rs if r["p99_ms"] <= bound]
+        return max(ok, key=lambda r: r["gkeys_per_s"]) if ok else None
+
+    curve = []
+    for ref in sorted(per, key=lambda r: r["p99_ms"]):
+        bound = ref["p99_ms"]
+        b, p = best(bat, bound), best(per, bound)
+        curve.append({"p99_bound_ms": round(bound, 3), "set_by_rate": ref["rate"],
+                      "per_request_gkeys": round(p["gkeys_per_s"], 3) if p else None,
+                      "batched_gkeys": round(b["gkeys_per_s"], 3) if b else None,
+                      "batched_rate": b["rate"] if b else None})
+    out = {"curve": curve}
+    ref = [c for c in curve if c["set_by_rate"] == ref_rate]
+    if ref:
+        out["at_ref"] = ref[0]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--rates", default="500,1000,2000,4000,8000,0")
+    ap.add_argument("--rates", default="500,1000,2000,4000,8000,16000,32000,0")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--capacity", type=int, default=1 << 30)
-    ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--capacity", type=int, default=1 << 29)
+    ap.add_argument("--streams", type=int, default=4)
     a = ap.parse_args()
-    sweep([float(r) for r in a.rates.split(",")], a.requests, a.warmup, a.capacity, a.streams)
+    rows = sweep([float(r) for r in a.rates.split(",")], a.requests, a.warmup, a.capacity, a.streams)
+    print(json.dumps({"gate": gate(rows)}), flush=True)
 
 
 if __name__ == "__main__":

@@ -42,16 +42,17 @@ def _alone(desc, k, v, n):
     return ko.cpu().numpy(), vo.cpu().numpy()
 
 
-@pytest.mark.parametrize("mode,streams", [(B.RS_SERVE_BATCHED, 2), (B.RS_SERVE_BATCHED, 1),
-                                          (B.RS_SERVE_PER_REQUEST, 3)])
-def test_mix_equals_alone(mode, streams):
+@pytest.mark.parametrize("mode,streams,min_batch", [(B.RS_SERVE_BATCHED, 2, 2), (B.RS_SERVE_BATCHED, 1, 0),
+                                                    (B.RS_SERVE_PER_REQUEST, 3, 0)])
+def test_mix_equals_alone(mode, streams, min_batch):
     import torch
     _say(f"server mix vs alone mode={mode} streams={streams}")
     desc = B.key_desc("u32", base=256, ndims=4)
     sizes = np.array(SIZES * 4)
     np.random.default_rng(3).shuffle(sizes)
     pool = make_pool(len(sizes), sizes, seed=99)
-    srv = Server(desc, capacity=int(sizes.sum()) + 1000, max_slots=len(sizes), streams=streams, mode=mode)
+    srv = Server(desc, capacity=int(sizes.sum()) + 1000, max_slots=len(sizes), streams=streams, mode=mode,
+                 min_batch=min_batch)
     try:
         tickets = [srv.submit(k, v) for k, v in pool]
         assert all(t is not None for t in tickets)
