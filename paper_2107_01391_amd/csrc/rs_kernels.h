@@ -26,6 +26,8 @@
 //                            rebuilt from its coordinates (eq. (16)).
 #pragma once
 
+#include <type_traits>
+
 #include "rs_device.h"
 
 namespace rs {
@@ -399,6 +401,18 @@ __device__ __forceinline__ void wave_rank(const Digit &digit, const K (&k)[KPT],
   }
 }
 
+// Element i of `base` through a 32-bit byte offset (an SGPR base plus a
+// 32-bit VGPR offset in the instruction) when i * sizeof(T) cannot reach
+// 2^32: element types of at most 4 bytes with i below 2^30.
+template <typename T>
+__device__ __forceinline__ T *elem32(T *base, uint32_t i) {
+  if constexpr (sizeof(T) <= 4) {
+    using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T *>(reinterpret_cast<Byte *>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+  } else
+    return base + i;
+}
+
 // Per cell d handled by this thread (d = t + j*BLOCK): the tile's count,
 // written to tot[j] and tstart[d], with wcnt[w][d] turned into the count of
 // d in waves before w.
@@ -512,15 +526,19 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
     }
   }
 
-  // ---- load: keys and values of this thread, striped by rounds
+  // ---- load: keys and values of this thread, striped by rounds (offsets
+  // within the tile are 32-bit)
   K k[KPT];
   uint32_t v[KPT];
-  const uint64_t wbase = elem0 + (uint64_t)wave * kWave * KPT + lane;
+  const K *ktile = kin + elem0;
+  const uint32_t *vtile = PAIRS ? vin + elem0 : nullptr;
+  const uint32_t count = (uint32_t)(end - elem0);
+  const uint32_t wfirst = wave * kWave * KPT + lane;
 #pragma unroll
   for (int r = 0; r < KPT; ++r) {
-    const uint64_t e = wbase + (uint64_t)r * kWave;
-    k[r] = e < end ? kin[e] : K{};
-    if constexpr (PAIRS) v[r] = e < end ? vin[e] : 0u;
+    const uint32_t e = wfirst + (uint32_t)r * kWave;
+    k[r] = e < count ? *elem32(ktile, e) : K{};
+    if constexpr (PAIRS) v[r] = e < count ? *elem32(vtile, e) : 0u;
   }
   if constexpr (MODE != kChained) __syncthreads();  // wcnt cleared
 
@@ -577,8 +595,11 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
   __syncthreads();
 
   // ---- write keys (and values): consecutive LDS entries of one cell go
-  // to consecutive output addresses
-  const uint32_t count = (uint32_t)(end - elem0);
+  // to consecutive output addresses; output offsets are relative to the
+  // array and below 2^30
+  K *karr = kout + out_base;
+  uint32_t *varr = PAIRS ? vout + out_base : nullptr;
+  const uint32_t alen = (uint32_t)(limit - out_base);
 #pragma unroll
   for (int r = 0; r < KPT; ++r) {
     const uint32_t i = t + r * BLOCK;
@@ -586,10 +607,10 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
       const K key = stage_k[i];
       const uint32_t d = p.digit(key);
       dg[r] = d;
-      const uint64_t at = out_base + gdelta[d] + i;
-      if (at < limit) {
-        kout[at] = key;
-        if constexpr (JOINT) vout[at] = stage_jv[i];
+      const uint32_t o = gdelta[d] + i;
+      if (o < alen) {
+        *elem32(karr, o) = key;
+        if constexpr (JOINT) *elem32(varr, o) = stage_jv[i];
       }
     }
   }
@@ -602,8 +623,8 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
 #pragma unroll
     for (int r = 0; r < KPT; ++r) {
       const uint32_t i = t + r * BLOCK;
-      const uint64_t at = out_base + gdelta[dg[r]] + i;
-      if (i < count && at < limit) vout[at] = stage_v[i];
+      const uint32_t o = gdelta[dg[r]] + i;
+      if (i < count && o < alen) *elem32(varr, o) = stage_v[i];
     }
   }
 }
