@@ -129,14 +129,9 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
   // dimension groups, least significant first
   uint32_t dims_per_pass;
   if (k.kind == RS_KEY_STR) {
+    // two characters per pass: 27^2 = 729 cells, the 10-bit kernels
     p.mode = kModeStr16;
-    dims_per_pass = 1;
-    while (dims_per_pass < 3) {
-      uint64_t c = 1;
-      for (uint32_t i = 0; i <= dims_per_pass; ++i) c *= 27;
-      if (c > tune.max_cells) break;
-      ++dims_per_pass;
-    }
+    dims_per_pass = 2;
   } else if (k.pow2) {
     p.mode = kModePow2;
     if (k.log2_base > 11) {
@@ -147,11 +142,11 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     if (dims_per_pass == 0) dims_per_pass = 1;
   } else {
     p.mode = (k.kind == RS_KEY_U32 || k.space_fits32) ? kModeDiv32 : kModeDiv64;
-    if (k.base > tune.max_cells) {
-      *why = "base above the per-pass cell limit";
+    if (k.base > 2048) {
+      *why = "a base above 2048 needs passes of more than 2048 cells";
       return RS_ERR_UNSUPPORTED;
     }
-    dims_per_pass = 1;
+    dims_per_pass = 1;  // at least one dimension per pass, whatever max_cells says
     for (;;) {
       uint64_t c = 1;
       for (uint32_t i = 0; i <= dims_per_pass; ++i) c *= k.base;

@@ -110,6 +110,8 @@ std::vector<Tuning> candidates(const rs_key_desc *desc, uint64_t n, bool batched
       t.digit_bits = d * m < 4 ? 4 : d * m;
       groupings.push_back(t);
     }
+  } else if (k.kind == RS_KEY_STR) {
+    groupings.push_back(Tuning());  // two characters per pass, fixed
   } else {
     uint64_t cells = k.base;
     for (uint32_t w = 1; w <= k.ndims && cells <= 2048; ++w, cells *= k.base) {

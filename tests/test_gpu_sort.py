@@ -94,6 +94,21 @@ def test_strings_keys_only():
     assert_same(gk, None, ok, None)
 
 
+@pytest.mark.parametrize("base,ndims,prescan", [(1000, 3, False), (1000, 3, True), (37, 6, True)])
+def test_other_bases(monkeypatch, base, ndims, prescan):
+    """Bases above the default pass width (1000 cells, the 10-bit kernels)
+    and an odd base with two-digit passes (37^2 = 1369 > 256: one digit)."""
+    monkeypatch.setenv("RS_PRESCAN_MIN_N", "1" if prescan else str(1 << 40))
+    _say(f"base {base} ndims {ndims} prescan={prescan}")
+    rng = np.random.default_rng(base)
+    n = 250_003
+    keys = rng.integers(0, base ** ndims, n, dtype=np.uint64).astype(np.uint32)
+    vals = np.arange(n, dtype=np.uint32)
+    gk, gv = gpu_sort(keys, vals, "u32", base, ndims)
+    ok, ov = oracle_sort(keys, vals, "u32", base, ndims)
+    assert_same(gk, gv, ok, ov)
+
+
 def test_u64_pairs():
     _say("u64 pairs")
     rng = np.random.default_rng(11)

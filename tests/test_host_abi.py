@@ -227,3 +227,13 @@ def test_server_work_bytes_and_create_checks_before_any_device_call():
     assert lib.rs_server_destroy(None) == 0
     t = ctypes.c_uint64(0)
     assert lib.rs_server_clock(ctypes.byref(t)) == 0 and t.value > 0
+
+
+def test_large_bases_plan_one_dimension_per_pass():
+    """A base above the default pass width still gets one dimension per pass
+    (up to 2048 cells); above 2048 it is refused."""
+    assert B.rs_temp_bytes(B.key_desc("u32", base=1000, ndims=3), 100_000, True) > 0
+    assert B.rs_temp_bytes(B.key_desc("u32", base=2048, ndims=2), 100_000, True) > 0
+    with pytest.raises(B.RSError) as e:
+        B.rs_temp_bytes(B.key_desc("u32", base=3000, ndims=2), 100_000, True)
+    assert e.value.status == 5
