@@ -17,12 +17,14 @@
  *
  * Dispatch.  A dispatcher thread launches work whenever one of `streams`
  * launch streams is idle:
- *   - RS_SERVE_BATCHED: every queued request (up to max_batch) in one
- *     segmented launch sequence, the rs_sort_batched kernels over
- *     begin/end ranges of the arena.  Fewer than min_batch queued requests
- *     run as single-array sorts instead, so light load costs what the
- *     baseline does; the segmented sequence pays off once enough requests
- *     share it.
+ *   - RS_SERVE_BATCHED: queued requests (up to max_batch) in one segmented
+ *     launch sequence, the rs_sort_batched kernels over begin/end ranges of
+ *     the arena.  While the queue holds no more requests than there are
+ *     streams, a request of more than batch_max_n keys at the head runs
+ *     alone and only the small requests at the head are batched, so small
+ *     requests do not wait for a large one's sort; with a longer queue
+ *     everything is batched.  Fewer than min_batch requests run as
+ *     single-array sorts, so light load costs what the baseline does.
  *   - RS_SERVE_PER_REQUEST: one rs_sort_pairs / rs_sort_keys launch per
  *     request (the baseline).
  *   - With streams > 1, launches overlap on the device.
@@ -63,6 +65,7 @@ typedef struct rs_server_config {
   uint32_t with_values;  /* requests carry uint32 values */
   uint32_t min_batch;    /* batched mode: fewer queued requests than this run as single-array sorts
                             in one launch slot (0 = 4) */
+  uint64_t batch_max_n;  /* batched mode, short queue: requests of more keys run alone (0 = 2^20) */
 } rs_server_config;
 
 typedef struct rs_server_stats {

@@ -65,7 +65,7 @@ class Tuning(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("capacity", ctypes.c_uint64), ("max_slots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
                 ("streams", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("with_values", ctypes.c_uint32),
-                ("min_batch", ctypes.c_uint32)]
+                ("min_batch", ctypes.c_uint32), ("batch_max_n", ctypes.c_uint64)]
 
 
 class ServerStats(ctypes.Structure):

@@ -271,13 +271,22 @@ struct rs_server {
       });
       if (stopping) return;
       const uint32_t i = (uint32_t)(std::find(stream_busy.begin(), stream_busy.end(), false) - stream_busy.begin());
-      const uint32_t take = cfg.mode == RS_SERVE_PER_REQUEST ? 1u : batch_cap(&cfg);
+      // per-request: the head alone.  Batched: while the queue is no longer
+      // than the launch streams (latency matters), a large head runs alone
+      // and only the run of small requests at the head is batched; with a
+      // backlog (throughput matters) everything queued is batched.  Queue
+      // order is kept.
+      const bool backlog = queue.size() > cfg.streams;
+      const uint64_t big = backlog ? ~0ull : (cfg.batch_max_n ? cfg.batch_max_n : (1ull << 20));
+      const bool alone = cfg.mode == RS_SERVE_PER_REQUEST || reqs[queue.front()].n > big;
+      const uint32_t take = alone ? 1u : batch_cap(&cfg);
       std::vector<uint64_t> tickets;
       std::vector<Span> spans;
       while (!queue.empty() && tickets.size() < take) {
         const uint64_t t = queue.front();
-        queue.pop_front();
         Request &r = reqs[t];
+        if (!alone && r.n > big) break;
+        queue.pop_front();
         r.state = kRunning;
         tickets.push_back(t);
         spans.push_back(Span{r.offset, r.n});

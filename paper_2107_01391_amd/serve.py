@@ -24,11 +24,12 @@ from . import _binding as B
 class Server:
     def __init__(self, desc: B.KeyDesc, capacity: int, max_slots: int = 256, streams: int = 2,
                  mode: int = B.RS_SERVE_BATCHED, with_values: bool = True, max_batch: int = 0,
-                 min_batch: int = 0):
+                 min_batch: int = 0, batch_max_n: int = 0):
         import torch
         B.load_library()
         self.desc = desc
-        self.cfg = B.ServerConfig(capacity, max_slots, max_batch, streams, mode, int(bool(with_values)), min_batch)
+        self.cfg = B.ServerConfig(capacity, max_slots, max_batch, streams, mode, int(bool(with_values)), min_batch,
+                                  batch_max_n)
         kb = {0: 4, 1: 8, 2: 8, 3: 16}[desc.kind]
         self.kb = kb
         dev = "cuda"

@@ -42,9 +42,10 @@ def _alone(desc, k, v, n):
     return ko.cpu().numpy(), vo.cpu().numpy()
 
 
-@pytest.mark.parametrize("mode,streams,min_batch", [(B.RS_SERVE_BATCHED, 2, 2), (B.RS_SERVE_BATCHED, 1, 0),
-                                                    (B.RS_SERVE_PER_REQUEST, 3, 0)])
-def test_mix_equals_alone(mode, streams, min_batch):
+@pytest.mark.parametrize("mode,streams,min_batch,batch_max_n", [
+    (B.RS_SERVE_BATCHED, 2, 2, 1 << 30), (B.RS_SERVE_BATCHED, 1, 0, 0), (B.RS_SERVE_BATCHED, 2, 0, 5000),
+    (B.RS_SERVE_PER_REQUEST, 3, 0, 0)])
+def test_mix_equals_alone(mode, streams, min_batch, batch_max_n):
     import torch
     _say(f"server mix vs alone mode={mode} streams={streams}")
     desc = B.key_desc("u32", base=256, ndims=4)
@@ -52,7 +53,7 @@ def test_mix_equals_alone(mode, streams, min_batch):
     np.random.default_rng(3).shuffle(sizes)
     pool = make_pool(len(sizes), sizes, seed=99)
     srv = Server(desc, capacity=int(sizes.sum()) + 1000, max_slots=len(sizes), streams=streams, mode=mode,
-                 min_batch=min_batch)
+                 min_batch=min_batch, batch_max_n=batch_max_n)
     try:
         tickets = [srv.submit(k, v) for k, v in pool]
         assert all(t is not None for t in tickets)
@@ -74,7 +75,7 @@ def test_mix_equals_alone(mode, streams, min_batch):
         assert st["p99_ms"] >= st["p50_ms"] > 0
         if mode == B.RS_SERVE_PER_REQUEST:
             assert st["launches"] == len(sizes)
-        else:
+        elif batch_max_n >= 1 << 30:
             assert st["launches"] < len(sizes)  # requests shared launches
     finally:
         srv.close()

@@ -187,7 +187,8 @@ def test_graph_capture_refuses_validation_and_null_out():
 # ------------------------------------------------------------------ server
 
 def _cfg(**kw):
-    c = dict(capacity=1 << 20, max_slots=64, max_batch=0, streams=2, mode=0, with_values=1, min_batch=0)
+    c = dict(capacity=1 << 20, max_slots=64, max_batch=0, streams=2, mode=0, with_values=1, min_batch=0,
+             batch_max_n=0)
     c.update(kw)
     return B.ServerConfig(*c.values())
 
