@@ -33,7 +33,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-KIND = {"u32": 0, "u64": 1, "fixed_i64": 2, "str": 3}
+KIND = {"u32": 0, "u64": 1, "fixed_i64": 2, "str": 3, "i32": 4, "i64": 5}
 ERRORS = {1: "bad argument", 2: "key outside the count space", 3: "count space too large",
           4: "out of memory", 5: "loop invariant violated"}
 
@@ -52,7 +52,7 @@ class OracleError(RuntimeError):
 
 class _Desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_uint32), ("base", ctypes.c_uint32),
-                ("ndims", ctypes.c_uint32), ("str_width", ctypes.c_uint32)]
+                ("ndims", ctypes.c_uint32), ("str_width", ctypes.c_uint32), ("order", ctypes.c_uint32)]
 
 
 class _Stats(ctypes.Structure):
@@ -141,8 +141,8 @@ def source() -> str:
         return f.read()
 
 
-def _desc(kind: str, base: int, ndims: int, str_width: int = 0) -> _Desc:
-    return _Desc(KIND[kind], base, ndims, str_width)
+def _desc(kind: str, base: int, ndims: int, str_width: int = 0, descending: bool = False) -> _Desc:
+    return _Desc(KIND[kind], base, ndims, str_width, 1 if descending else 0)
 
 
 def _ptr(a):
@@ -155,13 +155,15 @@ def _check(rc: int):
 
 
 def _key_array(keys: np.ndarray, kind: str) -> np.ndarray:
-    want = {"u32": np.uint32, "u64": np.uint64, "fixed_i64": np.int64, "str": np.uint8}[kind]
+    want = {"u32": np.uint32, "u64": np.uint64, "fixed_i64": np.int64, "str": np.uint8, "i32": np.int32,
+            "i64": np.int64}[kind]
     return np.ascontiguousarray(keys, dtype=want)
 
 
 def sort(keys: np.ndarray, vals: np.ndarray | None = None, *, kind: str, base: int, ndims: int,
-         groups: list[int] | None = None, str_width: int = 0):
-    """Returns (keys_out, vals_out or None, Stats).  Stable, ascending."""
+         groups: list[int] | None = None, str_width: int = 0, descending: bool = False):
+    """Returns (keys_out, vals_out or None, Stats).  Stable, ascending (or
+    descending: the mirrored walk, equal keys still in input order)."""
     lib = _load()
     keys = _key_array(keys, kind)
     n = keys.shape[0]
@@ -173,14 +175,14 @@ def sort(keys: np.ndarray, vals: np.ndarray | None = None, *, kind: str, base: i
     vin = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32)
     vout = None if vin is None else np.empty_like(vin)
     st = _Stats()
-    d = _desc(kind, base, ndims, str_width)
+    d = _desc(kind, base, ndims, str_width, descending)
     _check(lib.orc_sort(ctypes.byref(d), _ptr(keys), _ptr(out), _ptr(vin), _ptr(vout), n, _ptr(g), len(groups),
                         ctypes.byref(st)))
     return out, vout, Stats(st.cells_visited, st.spaces, st.max_depth)
 
 
 def sort_segments(keys: np.ndarray, vals: np.ndarray | None, offsets: np.ndarray, *, kind: str, base: int,
-                  ndims: int, groups: list[int] | None = None, str_width: int = 0):
+                  ndims: int, groups: list[int] | None = None, str_width: int = 0, descending: bool = False):
     """Sorts each segment [offsets[i], offsets[i+1]) on its own."""
     lib = _load()
     keys = _key_array(keys, kind)
@@ -191,7 +193,7 @@ def sort_segments(keys: np.ndarray, vals: np.ndarray | None, offsets: np.ndarray
     vin = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32)
     vout = None if vin is None else np.empty_like(vin)
     st = _Stats()
-    d = _desc(kind, base, ndims, str_width or (keys.shape[1] if keys.ndim == 2 else 0))
+    d = _desc(kind, base, ndims, str_width or (keys.shape[1] if keys.ndim == 2 else 0), descending)
     _check(lib.orc_sort_segments(ctypes.byref(d), _ptr(keys), _ptr(out), _ptr(vin), _ptr(vout), _ptr(offs),
                                  len(offs) - 1, _ptr(g), len(groups), ctypes.byref(st)))
     return out, vout, Stats(st.cells_visited, st.spaces, st.max_depth)

@@ -46,7 +46,13 @@
  *    is visited; "for z = 0 to S" emits exactly S copies.
  *  - Equal keys keep input order (stable), as the position arithmetic of
  *    counting sort gives.
- *  - Keys are non-negative; order is ascending.
+ *  - Keys are non-negative; order is ascending.  Beyond the paper (which is
+ *    silent on signs and on order): signed 32/64-bit integers are encoded
+ *    by adding 2^31 / 2^63 (offset binary, which maps the signed order onto
+ *    the unsigned one) before their digits are taken, and descending order
+ *    walks the same cells in the mirrored raster order (every coordinate
+ *    from its maximum down), with placement still in input order, so equal
+ *    keys keep their input order in both directions.
  *
  * Parity of every function here is pinned by the CPU tests (worked example
  * of Section 3 / Example 1, Table 3's space shapes, brute-force stable sort
@@ -56,7 +62,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { ORC_U32 = 0, ORC_U64 = 1, ORC_FIXED_I64 = 2, ORC_STR = 3 };
+enum { ORC_U32 = 0, ORC_U64 = 1, ORC_FIXED_I64 = 2, ORC_STR = 3, ORC_I32 = 4, ORC_I64 = 5 };
+enum { ORC_ASCENDING = 0, ORC_DESCENDING = 1 };
 enum {
   ORC_OK = 0,
   ORC_ERR_ARG = 1,      /* bad description / groups / pointers */
@@ -70,10 +77,11 @@ enum {
 #define ORC_MAX_CELLS (1ull << 26)
 
 typedef struct {
-  uint32_t kind;      /* ORC_U32 / ORC_U64 / ORC_FIXED_I64 / ORC_STR */
+  uint32_t kind;      /* ORC_U32 / ORC_U64 / ORC_FIXED_I64 / ORC_STR / ORC_I32 / ORC_I64 */
   uint32_t base;      /* b: radix of every dimension */
   uint32_t ndims;     /* N: digits per key */
   uint32_t str_width; /* bytes per key for strings (= N) */
+  uint32_t order;     /* ORC_ASCENDING or ORC_DESCENDING */
 } orc_desc;
 
 typedef struct {
@@ -93,10 +101,25 @@ typedef struct {
   uint64_t pw[ORC_MAX_DIMS + 1]; /* b^k, valid while it fits in 64 bits */
 } codec;
 
+/* The non-negative value whose base-b digits are the key's: the key itself,
+ * or for signed integers the key plus 2^31 / 2^63. */
+static uint64_t encoded(const codec *c, uint64_t i) {
+  switch (c->d.kind) {
+  case ORC_U32: return ((const uint32_t *)c->keys)[i];
+  case ORC_I32: return (uint64_t)((int64_t)((const int32_t *)c->keys)[i] + 2147483648LL);
+  case ORC_I64: return (uint64_t)((const int64_t *)c->keys)[i] ^ 0x8000000000000000ull;
+  case ORC_FIXED_I64: return (uint64_t)((const int64_t *)c->keys)[i];
+  default: return ((const uint64_t *)c->keys)[i];
+  }
+}
+
 /* Digit j (0 = most significant) of element i: the paper's F_Numeric(t[j]). */
 static uint32_t digit_of(const codec *c, uint64_t i, uint32_t j) {
   uint32_t n = c->d.ndims;
   switch (c->d.kind) {
+  case ORC_I32:
+  case ORC_I64:
+    return (uint32_t)((encoded(c, i) / c->pw[n - 1 - j]) % c->d.base);
   case ORC_U32: {
     uint64_t v = ((const uint32_t *)c->keys)[i];
     return (uint32_t)((v / c->pw[n - 1 - j]) % c->d.base);
@@ -128,6 +151,7 @@ static int key_valid(const codec *c, uint64_t i) {
   uint64_t v;
   if (c->d.kind == ORC_U32) v = ((const uint32_t *)c->keys)[i];
   else if (c->d.kind == ORC_U64) v = ((const uint64_t *)c->keys)[i];
+  else if (c->d.kind == ORC_I32 || c->d.kind == ORC_I64) v = encoded(c, i);
   else {
     int64_t s = ((const int64_t *)c->keys)[i];
     if (s < 0) return 0;
@@ -140,7 +164,7 @@ static int key_valid(const codec *c, uint64_t i) {
 static int codec_init(codec *c, const orc_desc *d, const void *keys) {
   if (!d || !keys) return ORC_ERR_ARG;
   if (d->ndims == 0 || d->ndims > ORC_MAX_DIMS || d->base < 2) return ORC_ERR_ARG;
-  if (d->kind > ORC_STR) return ORC_ERR_ARG;
+  if (d->kind > ORC_I64 || d->order > ORC_DESCENDING) return ORC_ERR_ARG;
   if (d->kind == ORC_STR && (d->base != 27 || d->str_width != d->ndims)) return ORC_ERR_ARG;
   c->d = *d;
   c->keys = keys;
@@ -273,20 +297,26 @@ static uint64_t extraction_walk(const codec *c, space *sp, uint64_t cnt, uint64_
   uint32_t b = c->d.base;
   sp->n_occupied = 0;
   if (cnt == 0) return 0;
+  const int down = c->d.order == ORC_DESCENDING;
   if (sp->w == 1) {
     if (!sp->hmin_flag[0]) return 0;
-    for (uint64_t x = sp->hmin[0]; x <= sp->hmax[0]; x++)
+    for (uint64_t t = 0; t <= sp->hmax[0] - sp->hmin[0]; t++) {
+      const uint64_t x = down ? sp->hmax[0] - t : sp->hmin[0] + t;
       if (visit(sp, x, &pos, cnt, k)) return pos;
+    }
     return pos;
   }
+  /* ascending: every coordinate from its minimum up; descending: the same
+   * bounds walked from the maximum down (the mirrored raster order) */
   uint32_t lo[ORC_MAX_DIMS], hi[ORC_MAX_DIMS], cur[ORC_MAX_DIMS];
-  for (uint32_t r = 0; r < b; r++) {
+  for (uint32_t t = 0; t < b; t++) {
+    const uint32_t r = down ? b - 1 - t : t;
     uint64_t row = (uint64_t)r * (sp->w - 1);
     if (!sp->hmin_flag[row]) continue; /* row never touched */
     for (uint32_t j = 1; j < sp->w; j++) {
       lo[j] = sp->hmin[row + j - 1];
       hi[j] = sp->hmax[row + j - 1];
-      cur[j] = lo[j];
+      cur[j] = down ? hi[j] : lo[j];
     }
     for (;;) {
       uint64_t cell = r;
@@ -295,11 +325,15 @@ static uint64_t extraction_walk(const codec *c, space *sp, uint64_t cnt, uint64_
       /* next coordinate vector: the last dimension counts fastest */
       int32_t j = (int32_t)sp->w - 1;
       while (j >= 1) {
-        if (cur[j] < hi[j]) {
+        if (!down && cur[j] < hi[j]) {
           cur[j]++;
           break;
         }
-        cur[j] = lo[j];
+        if (down && cur[j] > lo[j]) {
+          cur[j]--;
+          break;
+        }
+        cur[j] = down ? hi[j] : lo[j];
         j--;
       }
       if (j == 0) break;
@@ -333,10 +367,13 @@ static void write_rebuilt(sorter *s, uint64_t pos, uint64_t prefix, const space 
     }
     return;
   }
-  /* eq. (16): the element is its coordinates read as one base-b numeral */
+  /* eq. (16): the element is its coordinates read as one base-b numeral
+   * (signed keys: minus the bias their digits were taken with) */
   uint64_t v = prefix * c->pw[sp->w] + cell;
   if (c->d.kind == ORC_U32) ((uint32_t *)s->keys_out)[pos] = (uint32_t)v;
   else if (c->d.kind == ORC_U64) ((uint64_t *)s->keys_out)[pos] = v;
+  else if (c->d.kind == ORC_I32) ((int32_t *)s->keys_out)[pos] = (int32_t)((int64_t)v - 2147483648LL);
+  else if (c->d.kind == ORC_I64) ((uint64_t *)s->keys_out)[pos] = v ^ 0x8000000000000000ull;
   else ((int64_t *)s->keys_out)[pos] = (int64_t)v;
 }
 
@@ -345,7 +382,7 @@ static void copy_key(sorter *s, uint64_t pos, uint64_t elem) {
   if (c->d.kind == ORC_STR) {
     memcpy((uint8_t *)s->keys_out + pos * (uint64_t)c->d.str_width,
            (const uint8_t *)c->keys + elem * (uint64_t)c->d.str_width, c->d.str_width);
-  } else if (c->d.kind == ORC_U32) {
+  } else if (c->d.kind == ORC_U32 || c->d.kind == ORC_I32) {
     ((uint32_t *)s->keys_out)[pos] = ((const uint32_t *)c->keys)[elem];
   } else {
     ((uint64_t *)s->keys_out)[pos] = ((const uint64_t *)c->keys)[elem];
@@ -434,8 +471,8 @@ static void sorter_free(sorter *s) {
   free(s->tmp);
 }
 
-/* Sorts n keys (and their uint32 payload when vals_in is not NULL), ascending
- * and stable.  groups[0..ngroups) are the widths of the dimension groups of
+/* Sorts n keys (and their uint32 payload when vals_in is not NULL) in
+ * desc->order, stable.  groups[0..ngroups) are the widths of the dimension groups of
  * the hierarchy, most significant first; they must add up to N. */
 int orc_sort(const orc_desc *desc, const void *keys_in, void *keys_out, const uint32_t *vals_in,
              uint32_t *vals_out, uint64_t n, const uint32_t *groups, uint32_t ngroups, orc_stats *stats) {
@@ -496,7 +533,7 @@ int orc_sort_segments(const orc_desc *desc, const void *keys_in, void *keys_out,
                       uint32_t *vals_out, const uint64_t *offsets, uint32_t nseg, const uint32_t *groups,
                       uint32_t ngroups, orc_stats *stats) {
   orc_stats total = {0, 0, 0};
-  uint64_t width = desc->kind == ORC_STR ? desc->str_width : (desc->kind == ORC_U32 ? 4 : 8);
+  uint64_t width = desc->kind == ORC_STR ? desc->str_width : (desc->kind == ORC_U32 || desc->kind == ORC_I32 ? 4 : 8);
   for (uint32_t i = 0; i < nseg; i++) {
     uint64_t a = offsets[i], b = offsets[i + 1];
     if (b < a) return ORC_ERR_ARG;

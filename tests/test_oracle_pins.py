@@ -196,8 +196,57 @@ def pin_literal_walk_cost():
     assert st.cells_visited == 1
 
 
+_SIGNED_DESC_CASES = [
+    # kind, base, ndims, groups list, alphabet, descending
+    ("i32", 256, 4, [[1, 3], [1, 1, 1, 1]], [-2**31, -1, 0, 1, 2**31 - 1, -300], False),
+    ("i32", 10, 10, [[2] * 5, [4, 6]], [-2**31, -7, 0, 9, 2**31 - 1], False),
+    ("i64", 256, 8, [[1] * 8, [2, 2, 2, 2]], [-2**63, -2**40, -1, 0, 3, 2**63 - 1], False),
+    ("i64", 16, 16, [[4] * 4], [-2**63, -5, 0, 2**62], False),
+    ("u32", 10, 2, [[2], [1, 1]], [0, 7, 70, 77, 99], True),
+    ("u32", 256, 4, [[1, 3], [2, 2]], [0, 1, 256, 65536, 2**32 - 1], True),
+    ("fixed_i64", 10, 3, [[3], [1, 2]], [100, 101, 210, 9, 990], True),
+    ("i32", 256, 4, [[1, 3]], [-2**31, -1, 0, 1, 2**31 - 1], True),
+]
+
+
+def pin_signed_and_descending():
+    """Beyond the paper: signed integers (offset binary) follow the integers'
+    order, and descending order is the stable sort by decreasing key (equal
+    keys in input order), against Python's stable sort on tiny inputs."""
+    dts = {"u32": np.uint32, "fixed_i64": np.int64, "i32": np.int32, "i64": np.int64}
+    for kind, base, ndims, groupings, alphabet, desc in _SIGNED_DESC_CASES:
+        for alpha in itertools.combinations(alphabet, 3):
+            for length in range(0, 4):
+                for seq in itertools.product(alpha, repeat=length):
+                    keys = np.array(seq, dtype=dts[kind])
+                    vals = np.arange(length, dtype=np.uint32)
+                    order = sorted(range(length), key=lambda i: int(seq[i]), reverse=desc)
+                    for groups in groupings:
+                        ko, vo, _ = oracle.sort(keys, vals, kind=kind, base=base, ndims=ndims, groups=groups,
+                                                descending=desc)
+                        assert vo.tolist() == order, (kind, desc, groups, seq)
+                        assert ko.tolist() == [int(seq[i]) for i in order]
+                        ko2, _, _ = oracle.sort(keys, None, kind=kind, base=base, ndims=ndims, groups=groups,
+                                                descending=desc)
+                        assert ko2.tolist() == sorted((int(v) for v in seq), reverse=desc)
+    # strings, descending: reverse memcmp order of the padded rows
+    words = ["", "a", "ab", "b", "zz"]
+    for alpha in itertools.combinations(words, 3):
+        for length in range(0, 4):
+            for seq in itertools.product(alpha, repeat=length):
+                keys = _str_rows(seq, 2)
+                rows = [bytes(r) for r in keys]
+                order = sorted(range(length), key=lambda i: rows[i], reverse=True)
+                vals = np.arange(length, dtype=np.uint32)
+                for groups in ([2], [1, 1]):
+                    ko, vo, _ = oracle.sort(keys, vals, kind="str", base=27, ndims=2, groups=groups,
+                                            descending=True)
+                    assert vo.tolist() == order, (seq, groups)
+
+
 PINS = [pin_worked_example_output, pin_worked_example_hashing_state, pin_padding_example, pin_table3_shapes,
-        pin_brute_force_tiny, pin_brute_force_strings, pin_medium_vs_library_stable_sort, pin_literal_walk_cost]
+        pin_brute_force_tiny, pin_brute_force_strings, pin_medium_vs_library_stable_sort, pin_literal_walk_cost,
+        pin_signed_and_descending]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -207,14 +256,24 @@ def test_pin(pin):
 
 # Each mutation is (description, exact source text, replacement).
 MUTANTS = [
-    ("walk stops before the row maximum", "x <= sp->hmax[0]; x++", "x < sp->hmax[0]; x++"),
-    ("inner walk bound exclusive", "if (cur[j] < hi[j]) {", "if (cur[j] + 1 < hi[j]) {"),
+    ("walk stops before the row maximum", "t <= sp->hmax[0] - sp->hmin[0]; t++", "t < sp->hmax[0] - sp->hmin[0]; t++"),
+    ("inner walk bound exclusive", "if (!down && cur[j] < hi[j]) {", "if (!down && cur[j] + 1 < hi[j]) {"),
     ("H_Max comparison reversed", "if (sp->hmax[e] < coord[j]) sp->hmax[e] = coord[j];",
      "if (sp->hmax[e] > coord[j]) sp->hmax[e] = coord[j];"),
     ("H_Min never lowered", "} else if (sp->hmin[e] > coord[j]) {", "} else if (sp->hmin[e] < coord[j]) {"),
     ("digit index reversed", "return (uint32_t)((v / c->pw[n - 1 - j]) % c->d.base);\n  }\n  case ORC_U64",
      "return (uint32_t)((v / c->pw[j]) % c->d.base);\n  }\n  case ORC_U64"),
-    ("rows walked descending", "for (uint32_t r = 0; r < b; r++) {", "for (uint32_t r = b; r-- > 0;) {"),
+    ("rows walked descending", "const uint32_t r = down ? b - 1 - t : t;", "const uint32_t r = down ? t : b - 1 - t;"),
+    ("descending inner coordinates restart at the minimum", "cur[j] = down ? hi[j] : lo[j];\n        j--;",
+     "cur[j] = lo[j];\n        j--;"),
+    ("descending one-dimensional walk ascends", "const uint64_t x = down ? sp->hmax[0] - t : sp->hmin[0] + t;",
+     "const uint64_t x = sp->hmin[0] + t;"),
+    ("signed 32-bit keys without the bias",
+     "case ORC_I32: return (uint64_t)((int64_t)((const int32_t *)c->keys)[i] + 2147483648LL);",
+     "case ORC_I32: return (uint64_t)(uint32_t)((const int32_t *)c->keys)[i];"),
+    ("signed 64-bit keys without the bias",
+     "case ORC_I64: return (uint64_t)((const int64_t *)c->keys)[i] ^ 0x8000000000000000ull;",
+     "case ORC_I64: return (uint64_t)((const int64_t *)c->keys)[i];"),
     ("placement in reverse input order", "for (uint64_t i = 0; i < cnt; i++) {\n      uint64_t cell = element_cell",
      "for (uint64_t i = cnt; i-- > 0;) {\n      uint64_t cell = element_cell"),
     ("pad symbol sorts last", "return byte == 0 ? 0u : (uint32_t)(byte - 'a') + 1u;",
