@@ -73,10 +73,16 @@ typedef enum rs_key_kind {
   RS_KEY_U32 = 0,       /* uint32_t keys */
   RS_KEY_U64 = 1,       /* uint64_t keys */
   RS_KEY_FIXED_I64 = 2, /* int64_t fixed-point: value * 10^frac_digits, >= 0 */
-  RS_KEY_STR = 3        /* fixed-width byte strings, bytes in {0, 'a'..'z'} */
+  RS_KEY_STR = 3,       /* fixed-width byte strings, bytes in {0, 'a'..'z'} */
+  RS_KEY_I32 = 4,       /* int32_t keys, full range: digits of key + 2^31 */
+  RS_KEY_I64 = 5        /* int64_t keys, full range: digits of key + 2^63 */
 } rs_key_kind;
 
 #define RS_FLAG_VALIDATE 1u
+/* Descending order, still stable (equal keys keep their input order): every
+ * pass counts the complemented cell, cells - 1 - cell.  The paper's walk is
+ * ascending; this is its mirror. */
+#define RS_FLAG_DESCENDING 2u
 
 /* Describes the key and its count space (Section 3.1.1: the digits of a key
  * are the coordinates of its cell). */
@@ -91,7 +97,7 @@ typedef struct rs_key_desc {
                            places the decimal point only and does not change
                            the order */
   uint32_t str_width;   /* STR: bytes per key (16 supported); N = str_width */
-  uint32_t flags;       /* RS_FLAG_VALIDATE or 0 */
+  uint32_t flags;       /* RS_FLAG_VALIDATE | RS_FLAG_DESCENDING */
 } rs_key_desc;
 
 /* Scratch bytes that rs_sort_keys (with_values = 0) or rs_sort_pairs
@@ -135,7 +141,9 @@ rs_status rs_batched_temp_bytes(const rs_key_desc *desc, uint64_t total, uint32_
  * all arrays sharing every launch.  The launch shapes depend only on
  * (total, nseg), so a captured hipGraph can be replayed for any offsets with
  * the same (total, nseg).  Every array must hold at most RS_MAX_ELEMENTS
- * keys; total must be below 2^40. */
+ * keys; total must be below 2^40.  Offsets that break these rules give
+ * undefined results (reads outside keys_in); with RS_FLAG_VALIDATE they are
+ * checked first and give RS_ERR_BAD_DESC. */
 rs_status rs_sort_batched(const rs_key_desc *desc, const void *keys_in, void *keys_out, const uint32_t *vals_in,
                           uint32_t *vals_out, const uint64_t *d_seg_offsets, uint32_t nseg, uint64_t total, void *tmp,
                           size_t tmp_bytes, void *stream);

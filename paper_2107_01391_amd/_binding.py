@@ -16,11 +16,13 @@ LIB_PATH = os.path.join(_HERE, "librs.so")
 
 RS_OK = 0
 RS_ERR_NULL_ARG = 1
-RS_KEY_U32, RS_KEY_U64, RS_KEY_FIXED_I64, RS_KEY_STR = 0, 1, 2, 3
+RS_KEY_U32, RS_KEY_U64, RS_KEY_FIXED_I64, RS_KEY_STR, RS_KEY_I32, RS_KEY_I64 = 0, 1, 2, 3, 4, 5
 RS_FLAG_VALIDATE = 1
+RS_FLAG_DESCENDING = 2
 RS_MAX_ELEMENTS = (1 << 30) - 1
 
-KINDS = {"u32": RS_KEY_U32, "u64": RS_KEY_U64, "fixed_i64": RS_KEY_FIXED_I64, "str": RS_KEY_STR}
+KINDS = {"u32": RS_KEY_U32, "u64": RS_KEY_U64, "fixed_i64": RS_KEY_FIXED_I64, "str": RS_KEY_STR,
+         "i32": RS_KEY_I32, "i64": RS_KEY_I64}
 
 EXPORTED = ["rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_batched_temp_bytes", "rs_sort_batched",
             "rs_status_string", "rs_last_error", "rs_prof_enable", "rs_prof_query",
@@ -46,11 +48,12 @@ class KeyDesc(ctypes.Structure):
 
 
 def key_desc(kind: str | int, base: int = 0, ndims: int = 0, frac_digits: int = 0, str_width: int = 0,
-             validate: bool = False) -> KeyDesc:
+             validate: bool = False, descending: bool = False) -> KeyDesc:
     k = KINDS[kind] if isinstance(kind, str) else int(kind)
     if k == RS_KEY_STR and not str_width:
         str_width = 16
-    return KeyDesc(k, base, ndims, frac_digits, str_width, RS_FLAG_VALIDATE if validate else 0)
+    flags = (RS_FLAG_VALIDATE if validate else 0) | (RS_FLAG_DESCENDING if descending else 0)
+    return KeyDesc(k, base, ndims, frac_digits, str_width, flags)
 
 
 class Tuning(ctypes.Structure):

@@ -43,6 +43,40 @@ static rs_status batched_bits(const Plan &p, const Digit *d, const void *ki, voi
   }
 }
 
+// Offsets of the batched form: non-decreasing, from 0 to total, every array
+// at most RS_MAX_ELEMENTS keys.  Counts the violations into *bad.
+static __global__ __launch_bounds__(256) void rs_validate_offsets(const uint64_t *__restrict__ off, uint32_t nseg,
+                                                                  uint64_t total, uint32_t *__restrict__ bad) {
+  uint32_t mine = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i <= nseg; i += (uint64_t)gridDim.x * 256) {
+    const uint64_t a = off[i];
+    if (i == 0 && a != 0) ++mine;
+    if (i == nseg && a != total) ++mine;
+    if (i < nseg) {
+      const uint64_t b = off[i + 1];
+      if (b < a || b - a > RS_MAX_ELEMENTS) ++mine;
+    }
+  }
+  mine = wave_sum(mine);
+  if (lane_id() == 0 && mine) atomicAdd(bad, mine);
+}
+
+static rs_status validate_offsets(const uint64_t *off, uint32_t nseg, uint64_t total, void *tmp, hipStream_t s) {
+  uint32_t *bad = (uint32_t *)tmp;
+  rs_status st = launch_fill(bad, 16, 0, s);
+  if (st != RS_OK) return st;
+  uint64_t blocks = ((uint64_t)nseg + 256) / 256;
+  if (blocks > 1024) blocks = 1024;
+  RS_TIMED("rs_validate", s,
+           hipLaunchKernelGGL(rs_validate_offsets, dim3((uint32_t)blocks), dim3(256), 0, s, off, nseg, total, bad));
+  if ((st = check_launch("rs_validate_offsets")) != RS_OK) return st;
+  uint32_t h = 0;
+  if (hipMemcpyAsync(&h, bad, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return fail(RS_ERR_HIP, "validation copy");
+  if (h) return fail(RS_ERR_BAD_DESC, std::to_string(h) + " invalid segment offsets");
+  return RS_OK;
+}
+
 rs_status batched_run(const Plan &p, const void *ki, void *ko, const uint32_t *vi, uint32_t *vo,
                       const uint64_t *seg_lo, const uint64_t *seg_hi, void *tmp, hipStream_t s) {
   const uint32_t kb = p.key.key_bytes;
@@ -99,8 +133,8 @@ rs_status rs_sort_batched(const rs_key_desc *desc, const void *keys_in, void *ke
   if ((uintptr_t)d_seg_offsets % 8) return fail(RS_ERR_UNSUPPORTED, "d_seg_offsets must be 8-byte aligned");
   hipStream_t s = (hipStream_t)stream;
   if (desc->flags & RS_FLAG_VALIDATE) {
-    st = validate_keys(p, keys_in, total, tmp, s);
-    if (st != RS_OK) return st;
+    if ((st = validate_offsets(d_seg_offsets, nseg, total, tmp, s)) != RS_OK) return st;
+    if ((st = validate_keys(p, keys_in, total, tmp, s)) != RS_OK) return st;
   }
   // array i is [offsets[i], offsets[i + 1])
   return batched_run(p, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, d_seg_offsets + 1, tmp, s);

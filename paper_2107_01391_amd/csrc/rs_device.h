@@ -77,25 +77,36 @@ struct alignas(16) Str16 {
 
 // One pass's cell of a key: the group of dimensions [lo, lo + width) counted
 // from the least significant digit, as one row-major index in [0, b^width).
+// Every codec first adds `bias` to the key (signed keys: 2^31 or 2^63, which
+// maps the signed order onto the unsigned one; else 0) and, for descending
+// order, complements the cell: cells - 1 - cell, written (cell ^ cx) + ca
+// with (cx, ca) = (~0, cells), or (0, 0) ascending.
 //
-// Power-of-two base: a shift and a mask.
+// Power-of-two base: a shift and a mask (descending: xor with the mask).
 struct DigitPow2 {
   uint32_t shift, mask;
-  __host__ __device__ __forceinline__ uint32_t operator()(uint32_t v) const { return (v >> shift) & mask; }
+  uint32_t flip;  // mask when descending, else 0
+  uint64_t bias;
+  __host__ __device__ __forceinline__ uint32_t operator()(uint32_t v) const {
+    return (((v + (uint32_t)bias) >> shift) & mask) ^ flip;
+  }
   __host__ __device__ __forceinline__ uint32_t operator()(uint64_t v) const {
-    return (uint32_t)(v >> shift) & mask;
+    return ((uint32_t)((v + bias) >> shift) & mask) ^ flip;
   }
 };
 
 // Any base, values below 2^32: (v / b^lo) mod b^width with two invariant
-// divisions.  Used for u32 keys and for 64-bit keys whose whole space fits in
-// 32 bits (their high word is zero for every key inside the space).
+// divisions.  Used for 32-bit keys and for 64-bit keys whose whole space fits
+// in 32 bits (their high word is zero for every key inside the space).
 struct DigitDiv32 {
   FastDiv32 by_lo, by_cells;
   uint32_t cells;
+  uint32_t cx, ca;  // descending complement
+  uint64_t bias;
   __host__ __device__ __forceinline__ uint32_t operator()(uint32_t v) const {
-    uint32_t q = by_lo.div(v);
-    return q - by_cells.div(q) * cells;
+    v += (uint32_t)bias;
+    const uint32_t q = by_lo.div(v);
+    return ((q - by_cells.div(q) * cells) ^ cx) + ca;
   }
   __host__ __device__ __forceinline__ uint32_t operator()(uint64_t v) const { return (*this)((uint32_t)v); }
 };
@@ -104,9 +115,12 @@ struct DigitDiv32 {
 struct DigitDiv64 {
   FastDiv64 by_lo, by_cells;
   uint32_t cells;
+  uint32_t cx, ca;  // descending complement
+  uint64_t bias;
   __host__ __device__ __forceinline__ uint32_t operator()(uint64_t v) const {
-    uint64_t q = by_lo.div(v);
-    return (uint32_t)(q - by_cells.div(q) * cells);
+    v += bias;
+    const uint64_t q = by_lo.div(v);
+    return ((uint32_t)(q - by_cells.div(q) * cells) ^ cx) + ca;
   }
 };
 
@@ -114,6 +128,7 @@ struct DigitDiv64 {
 // group is the `width` symbols starting at byte `pos`, most significant first.
 struct DigitStr16 {
   uint32_t pos, width;
+  uint32_t cx, ca;  // descending complement
   __host__ __device__ __forceinline__ uint32_t operator()(const Str16 &k) const {
     uint64_t lo = (uint64_t)k.w[0] | ((uint64_t)k.w[1] << 32);
     uint64_t hi = (uint64_t)k.w[2] | ((uint64_t)k.w[3] << 32);
@@ -126,7 +141,7 @@ struct DigitStr16 {
       uint32_t sym = byte ? (byte - 96u < 26u ? byte - 96u : 26u) : 0u;
       cell = cell * 27u + sym;
     }
-    return cell;
+    return (cell ^ cx) + ca;
   }
 };
 

@@ -33,6 +33,18 @@ rs_status key_info(const rs_key_desc *desc, KeyInfo *ki, std::string *why) {
     ki->key_bytes = 8;
     ki->base = desc->base ? desc->base : 10;
     break;
+  case RS_KEY_I32:
+    ki->key_bytes = 4;
+    ki->base = desc->base ? desc->base : 256;
+    ki->is_signed = true;
+    ki->bias = 1ull << 31;
+    break;
+  case RS_KEY_I64:
+    ki->key_bytes = 8;
+    ki->base = desc->base ? desc->base : 256;
+    ki->is_signed = true;
+    ki->bias = 1ull << 63;
+    break;
   case RS_KEY_STR:
     if (desc->str_width != 16) {
       *why = "strings: only str_width == 16 is supported";
@@ -102,6 +114,15 @@ rs_status key_info(const rs_key_desc *desc, KeyInfo *ki, std::string *why) {
     }
   if (fits64) ki->space = sp;
   ki->space_fits32 = fits64 && sp <= (1ull << 32);
+  if (ki->is_signed) {
+    // every value of the type is a key: the space must cover 2^32 / 2^64
+    const bool covers = ki->key_bytes == 4 ? (!fits64 || sp >= (1ull << 32)) : !fits64;
+    if (!covers) {
+      *why = "signed keys need b^N to cover every value of the type";
+      return RS_ERR_BAD_DESC;
+    }
+  }
+  ki->descending = (desc->flags & RS_FLAG_DESCENDING) != 0;
   return RS_OK;
 }
 
@@ -120,7 +141,7 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
   p.n = n;
 
   // keys alone on a small integer space: the literal count / scan / emit
-  if (!pairs && k.kind != RS_KEY_STR && k.space && k.space <= kLiteralMaxCells &&
+  if (!pairs && k.kind != RS_KEY_STR && !k.is_signed && !k.descending && k.space && k.space <= kLiteralMaxCells &&
       k.space <= (n * 4 > 65536 ? n * 4 : 65536)) {
     p.literal = true;
     p.literal_cells = (uint32_t)k.space;
@@ -141,7 +162,7 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     dims_per_pass = tune.digit_bits / k.log2_base;
     if (dims_per_pass == 0) dims_per_pass = 1;
   } else {
-    p.mode = (k.kind == RS_KEY_U32 || k.space_fits32) ? kModeDiv32 : kModeDiv64;
+    p.mode = (k.key_bytes == 4 || k.space_fits32) ? kModeDiv32 : kModeDiv64;
     if (k.base > 2048) {
       *why = "a base above 2048 needs passes of more than 2048 cells";
       return RS_ERR_UNSUPPORTED;
@@ -172,20 +193,30 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     case kModePow2:
       p.p2[i].shift = lo * k.log2_base;
       p.p2[i].mask = (uint32_t)(cells - 1);
+      p.p2[i].flip = k.descending ? (uint32_t)(cells - 1) : 0u;
+      p.p2[i].bias = k.bias;
       break;
     case kModeDiv32:
       p.d32[i].by_lo = make_fastdiv32((uint32_t)below);
       p.d32[i].by_cells = make_fastdiv32((uint32_t)cells);
       p.d32[i].cells = (uint32_t)cells;
+      p.d32[i].cx = k.descending ? ~0u : 0u;
+      p.d32[i].ca = k.descending ? (uint32_t)cells : 0u;
+      p.d32[i].bias = k.bias;
       break;
     case kModeDiv64:
       p.d64[i].by_lo = make_fastdiv64(below);
       p.d64[i].by_cells = make_fastdiv64(cells);
       p.d64[i].cells = (uint32_t)cells;
+      p.d64[i].cx = k.descending ? ~0u : 0u;
+      p.d64[i].ca = k.descending ? (uint32_t)cells : 0u;
+      p.d64[i].bias = k.bias;
       break;
     case kModeStr16:
       p.s16[i].pos = k.ndims - lo - w;
       p.s16[i].width = w;
+      p.s16[i].cx = k.descending ? ~0u : 0u;
+      p.s16[i].ca = k.descending ? (uint32_t)cells : 0u;
       break;
     }
   }

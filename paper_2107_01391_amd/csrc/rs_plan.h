@@ -34,6 +34,9 @@ struct KeyInfo {
   uint32_t log2_base;
   bool space_fits32;    // b^N <= 2^32
   uint64_t space;       // b^N when it fits 64 bits, else 0
+  uint64_t bias;        // added before the digits are taken: 2^31 / 2^63 for signed keys
+  bool is_signed;       // RS_KEY_I32 / RS_KEY_I64
+  bool descending;      // RS_FLAG_DESCENDING
 };
 
 struct Tuning {

@@ -8,12 +8,12 @@ import oracle
 from paper_2107_01391_amd import _binding as B
 from paper_2107_01391_amd import api
 
-KEY_DTYPE = {"u32": np.uint32, "u64": np.uint64, "fixed_i64": np.int64}
+KEY_DTYPE = {"u32": np.uint32, "u64": np.uint64, "fixed_i64": np.int64, "i32": np.int32, "i64": np.int64}
 
 
-def desc_of(kind, base, ndims, str_width=0, frac_digits=0, validate=False):
+def desc_of(kind, base, ndims, str_width=0, frac_digits=0, validate=False, descending=False):
     return B.key_desc(kind, base=base, ndims=ndims, frac_digits=frac_digits, str_width=str_width,
-                      validate=validate)
+                      validate=validate, descending=descending)
 
 
 def key_shape(kind, n):
@@ -25,11 +25,11 @@ def key_dtype(kind):
 
 
 def gpu_sort(keys: np.ndarray, vals: np.ndarray | None, kind: str, base: int, ndims: int, *, in_place=False,
-             validate=False, frac_digits=0):
+             validate=False, frac_digits=0, descending=False):
     """Sorts on cuda:0 through rs_sort_pairs / rs_sort_keys; returns host arrays."""
     import torch
     n = keys.shape[0]
-    d = desc_of(kind, base, ndims, 16 if kind == "str" else 0, frac_digits, validate)
+    d = desc_of(kind, base, ndims, 16 if kind == "str" else 0, frac_digits, validate, descending)
     kd = api.to_device(keys)
     ko = kd if in_place else api.empty_device(kd.numel())
     if vals is None:
@@ -47,10 +47,10 @@ def gpu_sort(keys: np.ndarray, vals: np.ndarray | None, kind: str, base: int, nd
     return api.to_host(ko, key_dtype(kind), key_shape(kind, n)), api.to_host(vo, np.uint32, (n,))
 
 
-def oracle_sort(keys, vals, kind, base, ndims, groups=None):
+def oracle_sort(keys, vals, kind, base, ndims, groups=None, descending=False):
     if groups is None:
         groups = fast_groups(kind, base, ndims)
-    ko, vo, _ = oracle.sort(keys, vals, kind=kind, base=base, ndims=ndims, groups=groups)
+    ko, vo, _ = oracle.sort(keys, vals, kind=kind, base=base, ndims=ndims, groups=groups, descending=descending)
     return ko, vo
 
 

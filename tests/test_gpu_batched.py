@@ -168,3 +168,26 @@ def test_batched_graph_replay():
         torch.cuda.synchronize()
         assert float(junk) == float(junk)
         assert torch.equal(ko, eager_k) and torch.equal(vo, eager_v), f"replay {rep} differs from eager"
+
+
+@pytest.mark.parametrize("offs", [[0, 5, 3, 10], [1, 5, 7, 10], [0, 5, 7, 9]])
+def test_batched_validate_rejects_bad_offsets(offs):
+    """Decreasing offsets, a first offset other than 0, a last one other than
+    total: refused before any sort kernel runs (only with validation; the
+    offsets are never sorted with)."""
+    import torch
+    _say(f"batched validate offsets {offs}")
+    d = B.key_desc("u32", base=256, ndims=4, validate=True)
+    keys = np.arange(10, dtype=np.uint32)[::-1].copy()
+    kd, vd = api.to_device(keys), api.to_device(np.arange(10, dtype=np.uint32))
+    od = api.to_device(np.array(offs, np.uint64))
+    ko, vo = torch.empty_like(kd), torch.empty_like(vd)
+    tmp = api.empty_device(B.rs_batched_temp_bytes(d, 10, 3, True))
+    with pytest.raises(B.RSError) as e:
+        B.rs_sort_batched(d, kd, ko, vd, vo, od, 3, 10, tmp, tmp.numel())
+    assert e.value.status == 2 and "offsets" in str(e.value)
+    od.copy_(torch.from_numpy(np.array([0, 3, 3, 10], np.uint64).view(np.uint8)).cuda())
+    B.rs_sort_batched(d, kd, ko, vd, vo, od, 3, 10, tmp, tmp.numel())
+    torch.cuda.synchronize()
+    got = api.to_host(ko, np.uint32, (10,))
+    assert got.tolist() == sorted(keys[:3].tolist()) + sorted(keys[3:].tolist())

@@ -238,3 +238,18 @@ def test_large_bases_plan_one_dimension_per_pass():
     with pytest.raises(B.RSError) as e:
         B.rs_temp_bytes(B.key_desc("u32", base=3000, ndims=2), 100_000, True)
     assert e.value.status == 5
+
+
+def test_signed_kinds_need_a_covering_space():
+    assert B.rs_temp_bytes(B.key_desc("i32"), 1000, True) > 0
+    assert B.rs_temp_bytes(B.key_desc("i64", base=16), 1000, True) > 0
+    assert B.rs_temp_bytes(B.key_desc("i32", base=10, ndims=10), 1000, True) > 0
+    for d in (B.key_desc("i32", base=10, ndims=9), B.key_desc("i64", base=256, ndims=7)):
+        with pytest.raises(B.RSError) as e:
+            B.rs_temp_bytes(d, 1000, True)
+        assert e.value.status == 2
+    # descending keys only never takes the (ascending) literal form, whose
+    # scratch is the counts and starts of all 10^6 cells (8 MB)
+    asc = B.rs_temp_bytes(B.key_desc("u32", base=10, ndims=6), 10**6, False)
+    desc = B.rs_temp_bytes(B.key_desc("u32", base=10, ndims=6, descending=True), 10**6, False)
+    assert asc >= 8 * 10**6 and desc != asc
