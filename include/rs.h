@@ -37,8 +37,10 @@
  *     undefined.
  *   - n == 0 is a no-op returning RS_OK.  Counts are 32-bit on the device:
  *     one array holds at most RS_MAX_ELEMENTS keys.
- *   - Keys must lie in the count space: 0 <= key < b^N for integers and
- *     fixed-point values, bytes in {0, 'a'..'z'} for strings.  With
+ *   - Keys must lie in the count space: 0 <= key < b^N for unsigned integers
+ *     and fixed-point values, bytes in {0, 'a'..'z'} for base-27 strings
+ *     (every value of the type for signed integers and base-256 strings,
+ *     whose spaces cover the type).  With
  *     RS_FLAG_VALIDATE the library checks this first (a synchronous extra
  *     read) and returns RS_ERR_KEY_RANGE; without it, out-of-space keys give
  *     an unspecified order (never a fault).
@@ -73,7 +75,8 @@ typedef enum rs_key_kind {
   RS_KEY_U32 = 0,       /* uint32_t keys */
   RS_KEY_U64 = 1,       /* uint64_t keys */
   RS_KEY_FIXED_I64 = 2, /* int64_t fixed-point: value * 10^frac_digits, >= 0 */
-  RS_KEY_STR = 3,       /* fixed-width byte strings, bytes in {0, 'a'..'z'} */
+  RS_KEY_STR = 3,       /* fixed-width byte strings: base 27 (default), bytes in {0, 'a'..'z'};
+                           base 256, any bytes (memcmp order) */
   RS_KEY_I32 = 4,       /* int32_t keys, full range: digits of key + 2^31 */
   RS_KEY_I64 = 5        /* int64_t keys, full range: digits of key + 2^63 */
 } rs_key_kind;
@@ -89,7 +92,8 @@ typedef enum rs_key_kind {
 typedef struct rs_key_desc {
   uint32_t kind;        /* rs_key_kind */
   uint32_t base;        /* b, radix of one dimension; 0 = default: 256 for
-                           U32/U64, 10 for FIXED_I64, 27 for STR (pad + a..z) */
+                           U32/U64/I32/I64, 10 for FIXED_I64, 27 for STR
+                           (pad + a..z; 256 = any byte) */
   uint32_t ndims;       /* N, digits per key; 0 = default: enough for the
                            type (4 / 8 base-256 digits, 19 base-10 digits,
                            str_width symbols) */

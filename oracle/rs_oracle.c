@@ -13,7 +13,8 @@
  *     digits in base b, most significant first, left-padded with zeros.
  *     Integers and fixed-point decimals (value * 10^lambda, already scaled
  *     when stored) give their base-b digits by division; a fixed-width
- *     string gives one digit per byte, 0 (pad) -> 0 and 'a'..'z' -> 1..26.
+ *     string gives one digit per byte, 0 (pad) -> 0 and 'a'..'z' -> 1..26
+ *     (base 27), or the byte itself (base 256: memcmp order of any bytes).
  *  2. Hashing cycle (Section 3.1, eq. (1), and the n-digit version in the
  *     Supplementary section): for every element, in input order, the cell
  *     S[d1][d2]..[dw] of the count space is incremented, and the traverse
@@ -92,8 +93,16 @@ typedef struct {
 
 /* ---------------------------------------------------------------- codec */
 
-static uint32_t str_symbol(uint8_t byte) { return byte == 0 ? 0u : (uint32_t)(byte - 'a') + 1u; }
-static uint8_t str_byte(uint32_t sym) { return sym == 0 ? 0 : (uint8_t)('a' + sym - 1); }
+/* Strings over {pad, a..z} (base 27): pad -> 0, 'a'..'z' -> 1..26.  Strings
+ * over every byte (base 256): the byte itself, which is memcmp order. */
+static uint32_t str_symbol(uint32_t base, uint8_t byte) {
+  if (base == 256) return byte;
+  return byte == 0 ? 0u : (uint32_t)(byte - 'a') + 1u;
+}
+static uint8_t str_byte(uint32_t base, uint32_t sym) {
+  if (base == 256) return (uint8_t)sym;
+  return sym == 0 ? 0 : (uint8_t)('a' + sym - 1);
+}
 
 typedef struct {
   orc_desc d;
@@ -134,7 +143,7 @@ static uint32_t digit_of(const codec *c, uint64_t i, uint32_t j) {
   }
   default: {
     const uint8_t *row = (const uint8_t *)c->keys + i * (uint64_t)c->d.str_width;
-    return str_symbol(row[j]);
+    return str_symbol(c->d.base, row[j]);
   }
   }
 }
@@ -143,6 +152,7 @@ static uint32_t digit_of(const codec *c, uint64_t i, uint32_t j) {
 static int key_valid(const codec *c, uint64_t i) {
   uint32_t n = c->d.ndims;
   if (c->d.kind == ORC_STR) {
+    if (c->d.base == 256) return 1; /* every byte is a symbol */
     const uint8_t *row = (const uint8_t *)c->keys + i * (uint64_t)c->d.str_width;
     for (uint32_t j = 0; j < n; j++)
       if (row[j] != 0 && (row[j] < 'a' || row[j] > 'z')) return 0;
@@ -165,7 +175,7 @@ static int codec_init(codec *c, const orc_desc *d, const void *keys) {
   if (!d || !keys) return ORC_ERR_ARG;
   if (d->ndims == 0 || d->ndims > ORC_MAX_DIMS || d->base < 2) return ORC_ERR_ARG;
   if (d->kind > ORC_I64 || d->order > ORC_DESCENDING) return ORC_ERR_ARG;
-  if (d->kind == ORC_STR && (d->base != 27 || d->str_width != d->ndims)) return ORC_ERR_ARG;
+  if (d->kind == ORC_STR && ((d->base != 27 && d->base != 256) || d->str_width != d->ndims)) return ORC_ERR_ARG;
   c->d = *d;
   c->keys = keys;
   c->pw[0] = 1;
@@ -359,10 +369,10 @@ static void write_rebuilt(sorter *s, uint64_t pos, uint64_t prefix, const space 
   const codec *c = &s->c;
   if (c->d.kind == ORC_STR) {
     uint8_t *row = (uint8_t *)s->keys_out + pos * (uint64_t)c->d.str_width;
-    for (uint32_t j = 0; j < sp->dlo; j++) row[j] = str_byte(s->prefix_sym[j]);
+    for (uint32_t j = 0; j < sp->dlo; j++) row[j] = str_byte(c->d.base, s->prefix_sym[j]);
     uint64_t rest = cell;
     for (int32_t t = (int32_t)sp->w - 1; t >= 0; t--) {
-      row[sp->dlo + t] = str_byte((uint32_t)(rest % c->d.base));
+      row[sp->dlo + t] = str_byte(c->d.base, (uint32_t)(rest % c->d.base));
       rest /= c->d.base;
     }
     return;

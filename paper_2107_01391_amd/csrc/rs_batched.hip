@@ -29,9 +29,10 @@ static rs_status batched_bits(const Plan &p, const Digit *d, const void *ki, voi
   char *base = (char *)tmp;
   void *ak = base + p.seg.off_alt_keys;
   uint32_t *av = vi ? (uint32_t *)(base + p.seg.off_alt_vals) : nullptr;
-  if constexpr (sizeof(K) >= 16) {  // strings: 27^2 = 729 cells per pass
-    if (p.bits != 10) return fail(RS_ERR_UNSUPPORTED, "string passes use 10-bit cells");
-    return run_segmented<K, Digit, 10>(p, p.seg, d, ki, ko, vi, vo, ak, av, lo, hi, base, s);
+  if constexpr (sizeof(K) >= 16) {  // strings: 729 cells (base 27) or 256 (base 256) per pass
+    if (p.bits == 10) return run_segmented<K, Digit, 10>(p, p.seg, d, ki, ko, vi, vo, ak, av, lo, hi, base, s);
+    if (p.bits == 8) return run_segmented<K, Digit, 8>(p, p.seg, d, ki, ko, vi, vo, ak, av, lo, hi, base, s);
+    return fail(RS_ERR_UNSUPPORTED, "string passes use 8- or 10-bit cells");
   }
   switch (p.bits) {
   case 8:

@@ -124,11 +124,13 @@ struct DigitDiv64 {
   }
 };
 
-// Strings: one dimension per byte, pad (0) -> 0 and 'a'..'z' -> 1..26; the
-// group is the `width` symbols starting at byte `pos`, most significant first.
+// Strings: one dimension per byte; the group is the `width` symbols starting
+// at byte `pos`, most significant first.  Base 27: pad (0) -> 0 and
+// 'a'..'z' -> 1..26.  Base 256: the byte itself (memcmp order of any bytes).
 struct DigitStr16 {
   uint32_t pos, width;
   uint32_t cx, ca;  // descending complement
+  uint32_t base;    // 27 or 256
   __host__ __device__ __forceinline__ uint32_t operator()(const Str16 &k) const {
     uint64_t lo = (uint64_t)k.w[0] | ((uint64_t)k.w[1] << 32);
     uint64_t hi = (uint64_t)k.w[2] | ((uint64_t)k.w[3] << 32);
@@ -136,10 +138,14 @@ struct DigitStr16 {
     for (uint32_t i = 0; i < width; ++i) {
       uint32_t j = pos + i;
       uint32_t byte = (uint32_t)((j < 8 ? (lo >> (8 * j)) : (hi >> (8 * (j - 8)))) & 0xffu);
-      // 'a'..'z' -> 1..26; a byte outside the alphabet (invalid input) is
-      // clamped into the space so it can never index past the tables
-      uint32_t sym = byte ? (byte - 96u < 26u ? byte - 96u : 26u) : 0u;
-      cell = cell * 27u + sym;
+      if (base == 256) {
+        cell = cell * 256u + byte;
+      } else {
+        // 'a'..'z' -> 1..26; a byte outside the alphabet (invalid input) is
+        // clamped into the space so it can never index past the tables
+        uint32_t sym = byte ? (byte - 96u < 26u ? byte - 96u : 26u) : 0u;
+        cell = cell * 27u + sym;
+      }
     }
     return (cell ^ cx) + ca;
   }

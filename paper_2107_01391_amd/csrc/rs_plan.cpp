@@ -50,12 +50,12 @@ rs_status key_info(const rs_key_desc *desc, KeyInfo *ki, std::string *why) {
       *why = "strings: only str_width == 16 is supported";
       return RS_ERR_UNSUPPORTED;
     }
-    if (desc->base && desc->base != 27) {
-      *why = "strings: base must be 27 (pad + a..z)";
+    if (desc->base && desc->base != 27 && desc->base != 256) {
+      *why = "strings: base must be 27 (pad + a..z) or 256 (any byte)";
       return RS_ERR_BAD_DESC;
     }
     ki->key_bytes = 16;
-    ki->base = 27;
+    ki->base = desc->base ? desc->base : 27;
     ki->str_width = 16;
     if (desc->ndims && desc->ndims != 16) {
       *why = "strings: ndims must equal str_width";
@@ -150,9 +150,10 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
   // dimension groups, least significant first
   uint32_t dims_per_pass;
   if (k.kind == RS_KEY_STR) {
-    // two characters per pass: 27^2 = 729 cells, the 10-bit kernels
+    // base 27: two characters per pass (27^2 = 729 cells, the 10-bit
+    // kernels); base 256: one byte per pass (256 cells, the 8-bit kernels)
     p.mode = kModeStr16;
-    dims_per_pass = 2;
+    dims_per_pass = k.base == 27 ? 2 : 1;
   } else if (k.pow2) {
     p.mode = kModePow2;
     if (k.log2_base > 11) {
@@ -215,6 +216,7 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     case kModeStr16:
       p.s16[i].pos = k.ndims - lo - w;
       p.s16[i].width = w;
+      p.s16[i].base = k.base;
       p.s16[i].cx = k.descending ? ~0u : 0u;
       p.s16[i].ca = k.descending ? (uint32_t)cells : 0u;
       break;

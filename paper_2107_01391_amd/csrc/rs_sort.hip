@@ -198,9 +198,10 @@ static rs_status run_single(const Plan &pl, const Digit *digits, const void *ki,
 template <typename K, class Digit>
 static rs_status run_bits(const Plan &pl, const Digit *digits, const void *ki, void *ko, const uint32_t *vi,
                           uint32_t *vo, void *tmp, hipStream_t s) {
-  if constexpr (sizeof(K) >= 16) {  // strings: 27^2 = 729 cells per pass
-    if (pl.bits != 10) return fail(RS_ERR_UNSUPPORTED, "string passes use 10-bit cells");
-    return run_single<K, Digit, 10>(pl, digits, ki, ko, vi, vo, tmp, s);
+  if constexpr (sizeof(K) >= 16) {  // strings: 729 cells (base 27) or 256 (base 256) per pass
+    if (pl.bits == 10) return run_single<K, Digit, 10>(pl, digits, ki, ko, vi, vo, tmp, s);
+    if (pl.bits == 8) return run_single<K, Digit, 8>(pl, digits, ki, ko, vi, vo, tmp, s);
+    return fail(RS_ERR_UNSUPPORTED, "string passes use 8- or 10-bit cells");
   }
   switch (pl.bits) {
   case 8:
@@ -276,6 +277,7 @@ __global__ __launch_bounds__(256) void rs_validate(const K *__restrict__ keys, u
 
 rs_status validate_keys(const Plan &pl, const void *keys, uint64_t n, void *tmp, hipStream_t s) {
   if (pl.key.is_signed) return RS_OK;  // every value of the type is a key
+  if (pl.key.kind == RS_KEY_STR && pl.key.base == 256) return RS_OK;  // every byte is a symbol
   uint32_t *bad = (uint32_t *)tmp;
   if (hipMemsetAsync(bad, 0, 4, s) != hipSuccess) return fail(RS_ERR_HIP, "hipMemsetAsync");
   uint64_t blocks = (n + 255) / 256;

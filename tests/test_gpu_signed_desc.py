@@ -135,3 +135,44 @@ def test_batched_descending_and_signed(kind):
     dt = np.uint32 if kind == "u32" else np.int32
     assert np.array_equal(api.to_host(ko, dt, (total,)), ok)
     assert np.array_equal(api.to_host(vo, np.uint32, (total,)), ov)
+
+
+def _byte_rows(n, seed):
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, 256, (n, 16), dtype=np.uint8)
+    rows[:, 3:] = np.where(rng.random((n, 13)) < 0.3, 0, rows[:, 3:])  # padding-like zeros
+    if n > 2:
+        rows[::7] = rows[2]  # duplicates
+    return rows
+
+
+@pytest.mark.parametrize("desc", [False, True])
+@pytest.mark.parametrize("n", [1, 2049, 70_001])
+def test_byte_strings(form, desc, n):
+    """16-byte keys over every byte value (base 256): memcmp order."""
+    _say(f"byte strings n={n} desc={desc} {form}")
+    keys = _byte_rows(n, n)
+    vals = np.arange(n, dtype=np.uint32)
+    gk, gv = gpu_sort(keys, vals, "str", 256, 16, descending=desc)
+    ok, ov = oracle_sort(keys, vals, "str", 256, 16, descending=desc)
+    assert_same(gk, gv, ok, ov)
+    if n > 1:
+        rows = [bytes(r) for r in keys]
+        assert [bytes(r) for r in gk] == sorted(rows, reverse=desc)
+
+
+def test_byte_strings_batched_keys_only():
+    import torch
+    _say("byte strings batched keys only")
+    keys = _byte_rows(30_000, 5)
+    offs = np.array([0, 1, 2000, 2049, 10_000, 30_000], np.uint64)
+    d = B.key_desc("str", base=256, ndims=16)
+    kd, od = api.to_device(keys), api.to_device(offs)
+    ko = torch.empty_like(kd)
+    tmp = api.empty_device(B.rs_batched_temp_bytes(d, 30_000, 5, False))
+    B.rs_sort_batched(d, kd, ko, None, None, od, 5, 30_000, tmp, tmp.numel())
+    torch.cuda.synchronize()
+    got = api.to_host(ko, np.uint8, (30_000, 16))
+    for a, b in zip(offs[:-1], offs[1:]):
+        want = sorted(bytes(r) for r in keys[int(a):int(b)])
+        assert [bytes(r) for r in got[int(a):int(b)]] == want

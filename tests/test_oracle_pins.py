@@ -244,9 +244,30 @@ def pin_signed_and_descending():
                     assert vo.tolist() == order, (seq, groups)
 
 
+def pin_byte_strings():
+    """Beyond the paper: 16-byte strings over every byte value (base 256, one
+    dimension per byte) follow memcmp order, against Python's bytes order."""
+    rng = np.random.default_rng(11)
+    alphabet = [0, 1, ord("A"), ord("a"), 0x7F, 0x80, 0xFF]
+    for trial in range(40):
+        n = int(rng.integers(0, 40))
+        keys = rng.choice(alphabet, size=(n, 4)).astype(np.uint8)
+        keys[::3] = keys[0] if n else keys[::3]
+        rows = [bytes(r) for r in keys]
+        vals = np.arange(n, dtype=np.uint32)
+        for desc in (False, True):
+            order = sorted(range(n), key=lambda i: rows[i], reverse=desc)
+            for groups in ([1, 1, 1, 1], [2, 2], [1, 3]):
+                ko, vo, _ = oracle.sort(keys, vals, kind="str", base=256, ndims=4, groups=groups, descending=desc)
+                assert vo.tolist() == order, (trial, desc, groups)
+                assert [bytes(r) for r in ko] == [rows[i] for i in order]
+                ko2, _, _ = oracle.sort(keys, None, kind="str", base=256, ndims=4, groups=groups, descending=desc)
+                assert [bytes(r) for r in ko2] == sorted(rows, reverse=desc)
+
+
 PINS = [pin_worked_example_output, pin_worked_example_hashing_state, pin_padding_example, pin_table3_shapes,
         pin_brute_force_tiny, pin_brute_force_strings, pin_medium_vs_library_stable_sort, pin_literal_walk_cost,
-        pin_signed_and_descending]
+        pin_signed_and_descending, pin_byte_strings]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -278,6 +299,7 @@ MUTANTS = [
      "for (uint64_t i = cnt; i-- > 0;) {\n      uint64_t cell = element_cell"),
     ("pad symbol sorts last", "return byte == 0 ? 0u : (uint32_t)(byte - 'a') + 1u;",
      "return byte == 0 ? 26u : (uint32_t)(byte - 'a');"),
+    ("byte strings rebuilt from the 27-symbol alphabet", "  if (base == 256) return (uint8_t)sym;\n", ""),
     ("rebuilt key drops the prefix", "uint64_t v = prefix * c->pw[sp->w] + cell;", "uint64_t v = cell;"),
     ("untouched rows walked", "if (!sp->hmin_flag[row]) continue; /* row never touched */",
      "/* every row walked */"),
