@@ -259,6 +259,39 @@ __global__ __launch_bounds__(BLOCK) void rs_tile_histogram(const TileHistParams<
 
 // ------------------------------------------------------------- cell scan
 
+// Traverse maps of the literal form (Section 3.1): for each value r of the
+// leading coordinate (row r: cells r * inner .. r * inner + inner - 1) the
+// least and greatest offset of an occupied cell in the row.  The least is
+// kept complemented (nlo = ~lo, raised with atomicMax) so that one zero fill
+// starts both tables: an untouched row reads lo = ~0 > hi = 0.  A
+// one-dimensional space is one row.
+struct RowMaps {
+  uint32_t *nlo, *hi;  // [rows]
+  uint32_t rows, inner;
+  FastDiv32 by_inner;
+};
+
+// Largest row count of a literal space (b^2 <= 2^24 cells).
+constexpr uint32_t kMaxMapRows = 4096;
+
+// Whether some row's occupied range reaches cells [lo, hi): block-wide, the
+// same answer in every thread; always true without maps (m.nlo == nullptr).
+template <int BLOCK>
+__device__ __forceinline__ bool chunk_occupied(const RowMaps &m, uint64_t lo, uint64_t hi) {
+  if (!m.nlo) return true;
+  __shared__ uint32_t s_any;
+  if (threadIdx.x == 0) s_any = 0;
+  __syncthreads();
+  const uint32_t r0 = m.by_inner.div((uint32_t)lo), r1 = m.by_inner.div((uint32_t)(hi - 1));
+  for (uint32_t r = r0 + threadIdx.x; r <= r1; r += BLOCK) {
+    const uint32_t a = ~m.nlo[r], b = m.hi[r];
+    const uint64_t first = (uint64_t)r * m.inner + a, last = (uint64_t)r * m.inner + b;
+    if (a <= b && first < hi && last >= lo) s_any = 1;
+  }
+  __syncthreads();
+  return s_any != 0;
+}
+
 struct ScanParams {
   const uint32_t *in;       // counts: [nseg][stride]
   uint32_t nseg;            // independent scans
@@ -319,10 +352,16 @@ __device__ __forceinline__ uint64_t scan_count(uint64_t count, const uint32_t *c
 template <int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void rs_cell_scan_reduce(const uint32_t *__restrict__ in, uint64_t count_host,
                                                              const uint32_t *count_dev, uint32_t count_mul,
-                                                             uint32_t *__restrict__ sums) {
+                                                             uint32_t *__restrict__ sums, const RowMaps m) {
   const uint64_t count = scan_count(count_host, count_dev, count_mul);
   const uint64_t lo = (uint64_t)blockIdx.x * BLOCK * ITEMS;
   if (lo >= count) return;  // uniform
+  // literal form: a chunk no occupied range reaches sums to zero unread
+  const uint64_t hi_c = lo + (uint64_t)BLOCK * ITEMS < count ? lo + (uint64_t)BLOCK * ITEMS : count;
+  if (!chunk_occupied<BLOCK>(m, lo, hi_c)) {
+    if (threadIdx.x == 0) sums[blockIdx.x] = 0;
+    return;
+  }
   uint32_t s = 0;
 #pragma unroll
   for (int i = 0; i < ITEMS; ++i) {
@@ -361,13 +400,16 @@ __global__ __launch_bounds__(BLOCK) void rs_cell_scan_spine(uint32_t *__restrict
 template <int BLOCK, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void rs_cell_scan_down(const uint32_t *in, uint64_t count_host,
                                                            const uint32_t *count_dev, uint32_t count_mul,
-                                                           const uint32_t *__restrict__ sums, uint32_t *out) {
+                                                           const uint32_t *__restrict__ sums, uint32_t *out,
+                                                           const RowMaps m) {
   constexpr uint32_t CH = BLOCK * ITEMS;
   __shared__ uint32_t vals[CH];
   __shared__ uint32_t wsum[BLOCK / kWave];
   const uint64_t count = scan_count(count_host, count_dev, count_mul);
   const uint64_t lo = (uint64_t)blockIdx.x * CH;
   if (lo >= count) return;  // uniform
+  // literal form: no start is needed where nothing is emitted
+  if (!chunk_occupied<BLOCK>(m, lo, lo + CH < count ? lo + CH : count)) return;
   for (uint32_t i = threadIdx.x; i < CH; i += BLOCK) vals[i] = lo + i < count ? in[lo + i] : 0u;
   __syncthreads();
   block_exclusive_scan<BLOCK>(vals, CH, wsum);
@@ -635,7 +677,13 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
 // its N base-b coordinates).
 template <typename K, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void rs_cell_count(const K *__restrict__ keys, uint64_t n, uint32_t cells,
-                                                       uint32_t *__restrict__ counts) {
+                                                       uint32_t *__restrict__ counts, const RowMaps m) {
+  // the hashing cycle also updates the traverse maps: this workgroup's
+  // per-row least and greatest occupied offset, merged into m at the end
+  extern __shared__ uint32_t maps_lds[];  // [2][rows]
+  uint32_t *mnlo = maps_lds, *mhi = maps_lds + m.rows;
+  for (uint32_t r = threadIdx.x; r < 2 * m.rows; r += BLOCK) maps_lds[r] = 0;
+  __syncthreads();
   for (uint64_t e = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; e - threadIdx.x < n;
        e += (uint64_t)gridDim.x * BLOCK) {
     const bool valid = e < n;
@@ -650,7 +698,21 @@ __global__ __launch_bounds__(BLOCK) void rs_cell_count(const K *__restrict__ key
     } else if (valid) {
       atomicAdd(counts + c, 1u);
     }
+    // a row's extremes settle after a few keys: read before updating
+    if (valid) {
+      const uint32_t r = m.by_inner.div(c), off = c - r * m.inner;
+      if (~off > mnlo[r]) atomicMax(mnlo + r, ~off);
+      if (off > mhi[r]) atomicMax(mhi + r, off);
+    }
   }
+  __syncthreads();
+  // merged the same way: most workgroups find nothing to raise, and reads
+  // do not queue behind one address as atomics do
+  for (uint32_t r = threadIdx.x; r < m.rows; r += BLOCK)
+    if (mnlo[r]) {
+      if (mnlo[r] > m.nlo[r]) atomicMax(m.nlo + r, mnlo[r]);
+      if (mhi[r] > m.hi[r]) atomicMax(m.hi + r, mhi[r]);
+    }
 }
 
 // Writes counts[c] copies of key c at starts[c] (the extraction cycle's
@@ -659,11 +721,23 @@ __global__ __launch_bounds__(BLOCK) void rs_cell_count(const K *__restrict__ key
 template <typename K, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void rs_cell_emit(const uint32_t *__restrict__ counts,
                                                       const uint32_t *__restrict__ starts, uint32_t cells,
-                                                      K *__restrict__ out, uint64_t n) {
+                                                      K *__restrict__ out, uint64_t n, const RowMaps m) {
   constexpr uint32_t kSmall = 8;
   const uint32_t c = blockIdx.x * BLOCK + threadIdx.x;
+  // the extraction walk visits only the occupied range of each row: a wave
+  // whose 64 cells lie in one row, all outside its range, reads nothing
+  // (every count outside the ranges is zero, so the rest need no test)
+  const uint32_t cw = __builtin_amdgcn_readfirstlane(c - lane_id());
+  if (cw >= cells) return;  // uniform
+  const uint32_t cl = cw + kWave - 1 < cells ? cw + kWave - 1 : cells - 1;
+  const uint32_t ra = m.by_inner.div(cw), rb = m.by_inner.div(cl);
+  if (ra == rb) {
+    const uint32_t lo = ~m.nlo[ra], hi = m.hi[ra];
+    const uint32_t oa = cw - ra * m.inner, ob = cl - ra * m.inner;
+    if (lo > hi || ob < lo || oa > hi) return;  // uniform
+  }
   const uint32_t cnt = c < cells ? counts[c] : 0u;
-  const uint32_t st = c < cells ? starts[c] : 0u;
+  const uint32_t st = cnt ? starts[c] : 0u;
   if (cnt <= kSmall) {
     for (uint32_t z = 0; z < cnt; ++z)
       if (st + z < n) out[st + z] = (K)c;

@@ -47,15 +47,17 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
   if ((st = check_launch("rs_tile_histogram")) != RS_OK) return st;
 
   const uint32_t *cdev = SEG ? ntotal : nullptr;
+  RowMaps nomaps;
+  memset(&nomaps, 0, sizeof nomaps);
   RS_TIMED("rs_cell_scan", stream,
            hipLaunchKernelGGL((rs_cell_scan_reduce<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
-                              stream, table, count, cdev, cells, sums));
+                              stream, table, count, cdev, cells, sums, nomaps));
   RS_TIMED("rs_cell_scan", stream,
            hipLaunchKernelGGL((rs_cell_scan_spine<1024, kBigScanChunk>), dim3(1), dim3(1024), 0, stream, sums, count,
                               cdev, cells));
   RS_TIMED("rs_cell_scan", stream,
            hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
-                              stream, table, count, cdev, cells, sums, table));
+                              stream, table, count, cdev, cells, sums, table, nomaps));
   if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
 
   PassParams<Digit> pp;

@@ -126,27 +126,10 @@ rs_status key_info(const rs_key_desc *desc, KeyInfo *ki, std::string *why) {
   return RS_OK;
 }
 
-rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tuning &tune, Plan *plan,
-                    std::string *why) {
-  Plan &p = *plan;
-  p = Plan();
-  rs_status st = key_info(desc, &p.key, why);
-  if (st != RS_OK) return st;
-  if (n > RS_MAX_ELEMENTS) {
-    *why = "n exceeds RS_MAX_ELEMENTS (counts are 30-bit in the look-back words)";
-    return RS_ERR_UNSUPPORTED;
-  }
-  const KeyInfo &k = p.key;
-  p.pairs = pairs;
-  p.n = n;
-
-  // keys alone on a small integer space: the literal count / scan / emit
-  if (!pairs && k.kind != RS_KEY_STR && !k.is_signed && !k.descending && k.space && k.space <= kLiteralMaxCells &&
-      k.space <= (n * 4 > 65536 ? n * 4 : 65536)) {
-    p.literal = true;
-    p.literal_cells = (uint32_t)k.space;
-  }
-
+// The passes of a plan: how the N digit dimensions are grouped (one count
+// space per group, least significant group first), each group's codec, and
+// the kernel variant.  Fails when some pass would not fit the kernels.
+static rs_status plan_passes(const KeyInfo &k, const Tuning &tune, Plan &p, std::string *why) {
   // dimension groups, least significant first
   uint32_t dims_per_pass;
   if (k.kind == RS_KEY_STR) {
@@ -233,6 +216,44 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     return RS_ERR_UNSUPPORTED;
   }
 
+  return RS_OK;
+}
+
+rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tuning &tune, Plan *plan,
+                    std::string *why) {
+  Plan &p = *plan;
+  p = Plan();
+  rs_status st = key_info(desc, &p.key, why);
+  if (st != RS_OK) return st;
+  if (n > RS_MAX_ELEMENTS) {
+    *why = "n exceeds RS_MAX_ELEMENTS (counts are 30-bit in the look-back words)";
+    return RS_ERR_UNSUPPORTED;
+  }
+  const KeyInfo &k = p.key;
+  p.pairs = pairs;
+  p.n = n;
+
+  // keys alone on a small integer space: the literal count / scan / emit
+  if (!pairs && k.kind != RS_KEY_STR && !k.is_signed && !k.descending && k.space && k.space <= kLiteralMaxCells &&
+      k.space <= (n * 4 > 65536 ? n * 4 : 65536)) {
+    p.literal = true;
+    p.literal_cells = (uint32_t)k.space;
+    // traverse maps: one row per value of the leading coordinate
+    p.map_rows = k.ndims >= 2 ? k.base : 1;
+    p.map_inner = p.literal_cells / p.map_rows;
+  }
+
+  // the passes; a literal plan does not use them, so a shape the passes
+  // cannot take does not stop it
+  st = plan_passes(k, tune, p, why);
+  if (st != RS_OK && !p.literal) return st;
+  if (st != RS_OK) {
+    why->clear();
+    p.npasses = 0;
+    p.bins = 256;
+    p.bits = 8;
+  }
+
   // tile shape: 256 threads (chained), or the tuned width (prescanned);
   // keys per thread sized so that the LDS staging of one tile stays at
   // 32 KiB per 256 threads for wide keys
@@ -257,11 +278,14 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     return at;
   };
   if (p.literal) {
-    // counts and control words are contiguous so one fill clears both
-    p.scan_chunks = (p.literal_cells + kScanChunk - 1) / kScanChunk;
+    // counts and both traverse maps are contiguous: one zero fill clears
+    // them; the chunk sums are written whole
+    p.scan_chunks = (p.literal_cells + kBigScanChunk - 1) / kBigScanChunk;
     p.off_counts = take((size_t)p.literal_cells * 4);
-    p.off_ctrl = take(((size_t)p.scan_chunks + 1) * 4);
+    p.off_map_hi = take((size_t)p.map_rows * 4);
+    p.off_map_lo = take((size_t)p.map_rows * 4);
     p.ctrl_bytes = off - p.off_counts;
+    p.off_sums = take((size_t)p.scan_chunks * 4);
     p.off_starts = take((size_t)p.literal_cells * 4);
   } else if (p.prescanned) {
     p.off_keys_alt = take((size_t)n * k.key_bytes);

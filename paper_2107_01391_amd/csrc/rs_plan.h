@@ -72,6 +72,7 @@ struct Plan {
   bool pairs = false;
   bool literal = false;      // keys only, whole space counted at once
   uint32_t literal_cells = 0;
+  uint32_t map_rows = 1, map_inner = 0;  // literal: traverse-map rows and cells per row
   bool prescanned = false;   // passes without look-back
 
   DigitMode mode = kModePow2;
@@ -92,6 +93,7 @@ struct Plan {
   size_t off_keys_alt = 0, off_vals_alt = 0, off_dstart = 0, off_status = 0;
   size_t off_ctrl = 0, ctrl_bytes = 0, status_bytes = 0;
   size_t off_counts = 0, off_starts = 0;
+  size_t off_map_lo = 0, off_map_hi = 0;  // literal: traverse maps (complemented minima, maxima)
   size_t off_table = 0, off_sums = 0;  // prescanned: per-tile counts, chunk sums
   uint32_t scan_chunks = 0;            // chunks of the cell scan
   SegLayout seg;                       // batched form

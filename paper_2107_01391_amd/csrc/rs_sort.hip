@@ -111,6 +111,7 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
 
   // 3. exclusive scan of each pass's cells
   ScanParams s;
+  memset(&s, 0, sizeof s);  // no traverse maps unless set
   s.in = counts;
   s.nseg = pl.npasses;
   s.cells = pl.bins;
@@ -217,39 +218,48 @@ static rs_status run_literal(const Plan &pl, const void *keys_in, void *keys_out
   char *base = (char *)tmp;
   uint32_t *counts = (uint32_t *)(base + pl.off_counts);
   uint32_t *starts = (uint32_t *)(base + pl.off_starts);
-  uint32_t *ctrl = (uint32_t *)(base + pl.off_ctrl);
+  uint32_t *sums = (uint32_t *)(base + pl.off_sums);
+  if (pl.map_rows > kMaxMapRows) return fail(RS_ERR_UNSUPPORTED, "too many traverse-map rows");
+  RowMaps maps;
+  maps.nlo = (uint32_t *)(base + pl.off_map_lo);
+  maps.hi = (uint32_t *)(base + pl.off_map_hi);
+  maps.rows = pl.map_rows;
+  maps.inner = pl.map_inner;
+  maps.by_inner = make_fastdiv32(pl.map_inner);
   rs_status st = launch_fill(counts, pl.ctrl_bytes, 0, stream);
   if (st != RS_OK) return st;
+  // a few key rounds per workgroup so that the map merge stays small
   uint64_t blocks = (pl.n + 255) / 256;
-  const uint64_t cap = (uint64_t)cu_count() * 16;
+  const uint64_t cap = (uint64_t)cu_count() * 4;
   if (blocks > cap) blocks = cap;
+  const size_t map_lds = (size_t)2 * pl.map_rows * 4;  // per-workgroup row minima and maxima
   if (pl.key.key_bytes == 4)
-    RS_TIMED("rs_cell_count", stream, hipLaunchKernelGGL((rs_cell_count<uint32_t, 256>), dim3((uint32_t)blocks), dim3(256), 0, stream,
-                       (const uint32_t *)keys_in, pl.n, pl.literal_cells, counts));
+    RS_TIMED("rs_cell_count", stream, hipLaunchKernelGGL((rs_cell_count<uint32_t, 256>), dim3((uint32_t)blocks), dim3(256), map_lds, stream,
+                       (const uint32_t *)keys_in, pl.n, pl.literal_cells, counts, maps));
   else
-    RS_TIMED("rs_cell_count", stream, hipLaunchKernelGGL((rs_cell_count<uint64_t, 256>), dim3((uint32_t)blocks), dim3(256), 0, stream,
-                       (const uint64_t *)keys_in, pl.n, pl.literal_cells, counts));
+    RS_TIMED("rs_cell_count", stream, hipLaunchKernelGGL((rs_cell_count<uint64_t, 256>), dim3((uint32_t)blocks), dim3(256), map_lds, stream,
+                       (const uint64_t *)keys_in, pl.n, pl.literal_cells, counts, maps));
   if ((st = check_launch("rs_cell_count")) != RS_OK) return st;
-  ScanParams s;
-  s.in = counts;
-  s.nseg = 1;
-  s.cells = pl.literal_cells;
-  s.stride = pl.literal_cells;
-  s.out = starts;
-  s.chunk_counter = ctrl;
-  s.chunk_status = ctrl + 1;
-  s.chunks_per_seg = pl.scan_chunks;
-  s.nseg_dev = nullptr;
-  s.nseg_mul = 1;
-  RS_TIMED("rs_cell_scan", stream, hipLaunchKernelGGL((rs_cell_scan<kScanBlock, kScanItems>), dim3(pl.scan_chunks), dim3(kScanBlock), 0, stream, s));
+  // reduce-then-scan over the cells; chunks that no row's occupied range
+  // reaches are neither read nor written
+  const uint64_t cells = pl.literal_cells;
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan_reduce<kScanBlock, kBigScanItems>), dim3(pl.scan_chunks), dim3(kScanBlock),
+                              0, stream, counts, cells, nullptr, 1, sums, maps));
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan_spine<1024, kBigScanChunk>), dim3(1), dim3(1024), 0, stream, sums, cells,
+                              nullptr, 1));
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems>), dim3(pl.scan_chunks), dim3(kScanBlock), 0,
+                              stream, counts, cells, nullptr, 1, sums, starts, maps));
   if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
   const uint32_t eb = (pl.literal_cells + 255) / 256;
   if (pl.key.key_bytes == 4)
     RS_TIMED("rs_cell_emit", stream, hipLaunchKernelGGL((rs_cell_emit<uint32_t, 256>), dim3(eb), dim3(256), 0, stream, counts, starts,
-                       pl.literal_cells, (uint32_t *)keys_out, pl.n));
+                       pl.literal_cells, (uint32_t *)keys_out, pl.n, maps));
   else
     RS_TIMED("rs_cell_emit", stream, hipLaunchKernelGGL((rs_cell_emit<uint64_t, 256>), dim3(eb), dim3(256), 0, stream, counts, starts,
-                       pl.literal_cells, (uint64_t *)keys_out, pl.n));
+                       pl.literal_cells, (uint64_t *)keys_out, pl.n, maps));
   return check_launch("rs_cell_emit");
 }
 

@@ -58,6 +58,39 @@ def test_decimal_keys_literal(n):
     assert_same(gk, None, ok, None, f"n={n}")
 
 
+@pytest.mark.parametrize("case", ["clustered", "two_rows", "extremes", "one_key", "one_dim", "u64_rows"])
+def test_literal_traverse_maps(case):
+    """Keys only on small spaces, where the count kernel also builds the
+    traverse maps (each row's occupied range) and the scan and emit skip
+    what lies outside: sparse and clustered occupancy, the first and last
+    cells, a single key, a one-dimensional space (one row)."""
+    _say(f"literal traverse maps {case}")
+    rng = np.random.default_rng(len(case))
+    kind, base, ndims, dt = "u32", 16, 6, np.uint32
+    if case == "clustered":  # 2^22 keys inside 1/256 of a 2^24-cell space
+        keys = rng.integers(0x350000, 0x360000, 1 << 22, dtype=np.uint32)
+    elif case == "two_rows":  # rows 2 and 13, narrow columns
+        a = rng.integers(2 * 2**20 + 1000, 2 * 2**20 + 5000, 300_000, dtype=np.uint32)
+        b = rng.integers(13 * 2**20 + 777, 13 * 2**20 + 9000, 300_000, dtype=np.uint32)
+        keys = np.concatenate([a, b])
+        rng.shuffle(keys)
+    elif case == "extremes":
+        keys = rng.choice(np.array([0, 1, 2**24 - 2, 2**24 - 1], np.uint32), 200_000)
+    elif case == "one_key":
+        keys = np.full(100_000, 2**23 + 12345, np.uint32)
+    elif case == "one_dim":
+        base, ndims = 60_000, 1
+        keys = rng.integers(1000, 2000, 70_000, dtype=np.uint32)
+    else:
+        kind, base, ndims, dt = "u64", 10, 6, np.uint64
+        keys = rng.integers(400_000, 420_000, 250_000, dtype=np.uint64)
+    gk, _ = gpu_sort(keys.astype(dt), None, kind, base, ndims)
+    assert np.array_equal(gk, np.sort(keys.astype(dt)))
+    if keys.shape[0] <= 400_000:
+        ok, _ = oracle_sort(keys.astype(dt), None, kind, base, ndims)
+        assert_same(gk, None, ok, None)
+
+
 @pytest.mark.parametrize("n", [5000, 300_001])
 def test_decimal_pairs_base10(n):
     _say(f"decimal pairs base 10 n={n}")
