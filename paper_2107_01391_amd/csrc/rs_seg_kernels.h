@@ -9,6 +9,11 @@
 //   rs_small_sort     one workgroup per small array, every pass in LDS: count
 //                     the cells, scan them, place the keys -- the hashing and
 //                     extraction cycles of Sections 3.1 and 3.2 on chip
+//                     (16-byte keys)
+//   rs_local_sort     the same for 4- and 8-byte keys, by 4-bit sub-passes
+//                     over each cell index with per-thread counts (used when
+//                     there are two or more passes: one 8-bit pass is
+//                     cheaper as the ballot-ranked rs_small_sort)
 //   (the large arrays' passes are rs_tile_histogram, the cell scan and
 //   rs_rank_scatter<..., kPrescannedSeg>)
 #pragma once
@@ -184,6 +189,133 @@ __global__ __launch_bounds__(BLOCK) void rs_small_sort(const SmallParams<Digit> 
         if constexpr (PAIRS) vout[b + e] = v[r];
       }
     }
+  }
+}
+
+// Sorts whole arrays of at most BLOCK*KPT 4- or 8-byte keys, one per
+// workgroup iteration, by least-significant-first sub-passes of 4 bits over
+// each pass's cell index (a stable sort by the cell index is a stable sort
+// by the cell).  Thread t owns KPT consecutive positions, so the place of a
+// key is: the keys of smaller sub-digit, plus the keys of equal sub-digit
+// that earlier threads own, plus its rank among its own thread's equal keys.
+// That is stable without comparing lanes.  Per-thread counts are 16 fields
+// of 8 bits in two 64-bit registers; one LDS scan of the [sub-digit][thread]
+// table turns them into starts.  LDS arrays are padded one word in 16 so
+// that the blocked and striped accesses are free of bank conflicts.
+template <typename K, class Digit, int BLOCK, int KPT, bool PAIRS>
+__global__ __launch_bounds__(BLOCK, 4) void rs_local_sort(const SmallParams<Digit> sp, const K *__restrict__ kin,
+                                                       K *__restrict__ kout, const uint32_t *__restrict__ vin,
+                                                       uint32_t *__restrict__ vout) {
+  static_assert(sizeof(K) <= 8 && KPT <= 16 && BLOCK % kWave == 0, "tile shape");
+  constexpr uint32_t TILE = BLOCK * KPT;
+  constexpr uint32_t NT = 16 * BLOCK;  // [sub-digit][thread]
+  __shared__ K stage_k[TILE + TILE / 16];
+  __shared__ uint32_t stage_v[PAIRS ? TILE + TILE / 16 : 1];
+  __shared__ uint32_t tab[NT + NT / 16];
+  __shared__ uint32_t wsum[BLOCK / kWave];
+  const uint32_t t = threadIdx.x, lane = t % kWave, wave = t / kWave;
+  const uint32_t first = t * KPT;
+  const uint32_t nsmall = *sp.nsmall;
+  for (uint32_t idx = blockIdx.x; idx < nsmall; idx += gridDim.x) {
+    const uint32_t sid = sp.small_ids[idx];
+    const uint64_t b = sp.seg_lo[sid];
+    const uint32_t len = (uint32_t)(sp.seg_hi[sid] - b);
+    const uint32_t nv = first >= len ? 0u : (len - first < (uint32_t)KPT ? len - first : (uint32_t)KPT);
+    // coalesced loads into LDS, then each thread takes its own run
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+      const uint32_t e = r * BLOCK + t;
+      if (e < len) {
+        stage_k[e + (e >> 4)] = kin[b + e];
+        if constexpr (PAIRS) stage_v[e + (e >> 4)] = vin[b + e];
+      }
+    }
+    __syncthreads();
+    K k[KPT];
+    uint32_t v[KPT];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const uint32_t i = first + j;
+      if ((uint32_t)j < nv) {
+        k[j] = stage_k[i + (i >> 4)];
+        if constexpr (PAIRS) v[j] = stage_v[i + (i >> 4)];
+      }
+    }
+    for (uint32_t pass = 0; pass < sp.npasses; ++pass) {
+      const uint32_t cells = sp.pass_cells[pass];
+      const uint32_t nbits = cells > 1 ? 32u - (uint32_t)__builtin_clz(cells - 1) : 0u;
+      for (uint32_t shift = 0; shift < nbits; shift += 4) {
+        // this thread's counts per sub-digit, and each key's rank among them
+        uint64_t c_lo = 0, c_hi = 0;
+        uint32_t rd[KPT];
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+          if ((uint32_t)j < nv) {
+            const uint32_t d = (sp.digit[pass](k[j]) >> shift) & 15u;
+            const uint32_t sh = (d & 7u) * 8u;
+            const bool high = d >= 8;
+            const uint32_t r = (uint32_t)((high ? c_hi : c_lo) >> sh) & 0xffu;
+            const uint64_t inc = 1ull << sh;
+            c_lo += high ? 0ull : inc;
+            c_hi += high ? inc : 0ull;
+            rd[j] = d << 8 | r;
+          }
+        }
+#pragma unroll
+        for (uint32_t d = 0; d < 16; ++d) {
+          const uint32_t i = d * BLOCK + t;
+          tab[i + (i >> 4)] = (uint32_t)((d < 8 ? c_lo : c_hi) >> ((d & 7u) * 8u)) & 0xffu;
+        }
+        __syncthreads();
+        // exclusive scan of the table in [sub-digit][thread] order: thread
+        // t owns flat entries 16t .. 16t+15 (padded: 17t .. 17t+15)
+        uint32_t own[16], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          own[q] = tab[17 * t + q];
+          sum += own[q];
+        }
+        const uint32_t incl = wave_inclusive_scan(sum);
+        if (lane == kWave - 1) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t run = incl - sum;
+        for (uint32_t w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          tab[17 * t + q] = run;
+          run += own[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+          if ((uint32_t)j < nv) {
+            const uint32_t i = (rd[j] >> 8) * BLOCK + t;
+            const uint32_t pos = tab[i + (i >> 4)] + (rd[j] & 0xffu);
+            stage_k[pos + (pos >> 4)] = k[j];
+            if constexpr (PAIRS) stage_v[pos + (pos >> 4)] = v[j];
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+          const uint32_t i = first + j;
+          if ((uint32_t)j < nv) {
+            k[j] = stage_k[i + (i >> 4)];
+            if constexpr (PAIRS) v[j] = stage_v[i + (i >> 4)];
+          }
+        }
+      }
+    }
+    // stage holds the sorted array (or the input when no pass has cells)
+#pragma unroll
+    for (int r = 0; r < KPT; ++r) {
+      const uint32_t e = r * BLOCK + t;
+      if (e < len) {
+        kout[b + e] = stage_k[e + (e >> 4)];
+        if constexpr (PAIRS) vout[b + e] = stage_v[e + (e >> 4)];
+      }
+    }
+    __syncthreads();
   }
 }
 

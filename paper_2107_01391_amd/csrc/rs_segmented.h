@@ -3,7 +3,8 @@
 //
 //   1. rs_seg_plan       split arrays into small / large, number large tiles
 //   2. rs_seg_tiles      resolve every large-array tile once
-//   3. rs_small_sort     small arrays sorted whole in LDS (one workgroup each)
+//   3. rs_small_sort / rs_local_sort
+//                        small arrays sorted whole in LDS (one workgroup each)
 //   4. per pass over the large arrays: rs_tile_histogram, one scan of the
 //      table, rs_rank_scatter (rs_passes.h)
 //
@@ -63,14 +64,32 @@ rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, 
   sp.seg_hi = seg_hi;
   sp.small_ids = small_ids;
   sp.nsmall = nsmall;
-  if (pairs)
-    RS_TIMED("rs_small_sort", stream,
-             hipLaunchKernelGGL((rs_small_sort<K, Digit, BITS, 256, KPT, true>), dim3(L.small_grid), dim3(256), 0,
-                                stream, sp, (const K *)keys_in, (K *)keys_out, vals_in, vals_out));
-  else
-    RS_TIMED("rs_small_sort", stream,
-             hipLaunchKernelGGL((rs_small_sort<K, Digit, BITS, 256, KPT, false>), dim3(L.small_grid), dim3(256), 0,
-                                stream, sp, (const K *)keys_in, (K *)keys_out, nullptr, nullptr));
+  bool launched = false;
+  if constexpr (sizeof(K) <= 8) {
+    // several passes: 4-bit sub-passes with per-thread counts issue fewer
+    // instructions per key than ballot ranking; one pass is cheaper ranked
+    if (P >= 2) {
+      if (pairs)
+        RS_TIMED("rs_small_sort", stream,
+                 hipLaunchKernelGGL((rs_local_sort<K, Digit, 256, 16, true>), dim3(L.small_grid), dim3(256), 0,
+                                    stream, sp, (const K *)keys_in, (K *)keys_out, vals_in, vals_out));
+      else
+        RS_TIMED("rs_small_sort", stream,
+                 hipLaunchKernelGGL((rs_local_sort<K, Digit, 256, 16, false>), dim3(L.small_grid), dim3(256), 0,
+                                    stream, sp, (const K *)keys_in, (K *)keys_out, nullptr, nullptr));
+      launched = true;
+    }
+  }
+  if (!launched) {
+    if (pairs)
+      RS_TIMED("rs_small_sort", stream,
+               hipLaunchKernelGGL((rs_small_sort<K, Digit, BITS, 256, KPT, true>), dim3(L.small_grid), dim3(256), 0,
+                                  stream, sp, (const K *)keys_in, (K *)keys_out, vals_in, vals_out));
+    else
+      RS_TIMED("rs_small_sort", stream,
+               hipLaunchKernelGGL((rs_small_sort<K, Digit, BITS, 256, KPT, false>), dim3(L.small_grid), dim3(256), 0,
+                                  stream, sp, (const K *)keys_in, (K *)keys_out, nullptr, nullptr));
+  }
   if ((st = check_launch("rs_small_sort")) != RS_OK) return st;
 
   // large arrays: the passes, every array sharing each launch
