@@ -217,7 +217,7 @@ __global__ __launch_bounds__(BLOCK) void rs_tile_histogram(const TileHistParams<
       // when the array does
       constexpr int VEC = 16 / sizeof(K);
       const bool aligned = ((uintptr_t)keys % 16) == 0;
-      constexpr int UNROLL = TILE / (BLOCK * VEC) < 4 ? TILE / (BLOCK * VEC) : 4;
+      constexpr int UNROLL = TILE / (BLOCK * VEC) < 8 ? TILE / (BLOCK * VEC) : 8;
       for (uint64_t base = sp.elem0; base < sp.end; base += (uint64_t)BLOCK * VEC * UNROLL) {
         K k[UNROLL][VEC];
         bool valid[UNROLL][VEC];

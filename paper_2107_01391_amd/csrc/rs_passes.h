@@ -18,6 +18,9 @@
 namespace rs {
 
 constexpr int kTilesPerHistBlock = 8;
+// LDS of the per-tile count tables: two lane-group copies of eight 256-cell
+// tables, small enough for eight workgroups per CU
+constexpr uint32_t kTileHistBudget = 24 * 1024;
 
 template <typename K, class Digit, int BITS, int BLOCK, bool SEG>
 rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const K *src, K *dst,
@@ -35,7 +38,7 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
   th.digit = digit;
   th.cells = cells;
   th.ntiles = (uint32_t)ntiles_bound;
-  th.copies = count_copies(cells * TPW, kLdsCountBudget);
+  th.copies = count_copies(cells * TPW, kTileHistBudget);
   th.n = n;
   th.counts = table;
   th.tiles = tiles;
