@@ -15,6 +15,7 @@ rs_status make_batched(const rs_key_desc *desc, uint64_t total, uint64_t extent,
   if (st != RS_OK) return st;
   p->pairs = pairs;
   p->literal = false;
+  p->local = false;
   p->prescanned = false;
   st = make_seg_layout(*p, p->npasses, total, extent, nseg, true, prescan_block(tune, p->key.key_bytes, p->bits),
                        &p->seg, why);

@@ -29,7 +29,6 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
                           hipStream_t stream) {
   constexpr int KPT = sizeof(K) >= 16 ? 8 : 16;  // LDS staging: 32 KiB per 256 threads
   constexpr int TILE = BLOCK * KPT;
-  constexpr int TPW = kTilesPerHistBlock;
   rs_status st;
   const uint64_t count = (uint64_t)cells * ntiles_bound;
   const uint32_t nchunks = (uint32_t)((count + kBigScanChunk - 1) / kBigScanChunk);
@@ -38,15 +37,21 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
   th.digit = digit;
   th.cells = cells;
   th.ntiles = (uint32_t)ntiles_bound;
-  th.copies = count_copies(cells * TPW, kTileHistBudget);
   th.n = n;
   th.counts = table;
   th.tiles = tiles;
   th.ntotal = ntotal;
-  const size_t lds = (size_t)TPW * th.copies * (cells + 1) * 4;
-  RS_TIMED("rs_tile_histogram", stream,
-           hipLaunchKernelGGL((rs_tile_histogram<K, Digit, 256, TPW, TILE, SEG>),
-                              dim3((uint32_t)((ntiles_bound + TPW - 1) / TPW)), dim3(256), lds, stream, th, src));
+  auto histogram = [&]<int TPW>() {
+    th.copies = count_copies(cells * TPW, kTileHistBudget);
+    const size_t lds = (size_t)TPW * th.copies * (cells + 1) * 4;
+    RS_TIMED("rs_tile_histogram", stream,
+             hipLaunchKernelGGL((rs_tile_histogram<K, Digit, 256, TPW, TILE, SEG>),
+                                dim3((uint32_t)((ntiles_bound + TPW - 1) / TPW)), dim3(256), lds, stream, th, src));
+  };
+  // several tiles per workgroup once there are enough tiles to fill every
+  // CU with them; one tile each below that
+  if (ntiles_bound >= (uint64_t)cu_count() * 32) histogram.template operator()<kTilesPerHistBlock>();
+  else histogram.template operator()<1>();
   if ((st = check_launch("rs_tile_histogram")) != RS_OK) return st;
 
   const uint32_t *cdev = SEG ? ntotal : nullptr;

@@ -252,20 +252,26 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     p.npasses = 0;
     p.bins = 256;
     p.bits = 8;
+  } else if (n <= kLocalMaxN && k.key_bytes <= 8) {
+    // a short array: every pass on chip in one workgroup, one launch
+    p.local = true;
+    p.literal = false;
   }
 
   // tile shape: 256 threads (chained), or the tuned width (prescanned);
   // keys per thread sized so that the LDS staging of one tile stays at
   // 32 KiB per 256 threads for wide keys
-  p.prescanned = !p.literal && n >= tune.prescan_min_n;
+  p.prescanned = !p.literal && !p.local && n >= tune.prescan_min_n;
   p.block = p.prescanned ? prescan_block(tune, k.key_bytes, p.bits) : 256;
   p.kpt = k.key_bytes >= 16 ? 8 : 16;
   p.tile = p.block * p.kpt;
   p.ntiles = (n + p.tile - 1) / p.tile;
 
-  // histogram grid: enough workgroups to fill 256 CUs
+  // histogram grid: enough workgroups to fill 256 CUs, down to 4096 keys
+  // each for small arrays
   const uint64_t words = (uint64_t)p.npasses * p.bins;
   uint64_t g = (n + 16383) / 16384;
+  if (g < 256) g = (n + 4095) / 4096 < 256 ? (n + 4095) / 4096 : 256;
   if (g > 1024) g = 1024;
   if (g < 1) g = 1;
   p.hist_grid = (uint32_t)g;
@@ -277,7 +283,9 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     off = align_up(off + bytes, 256);
     return at;
   };
-  if (p.literal) {
+  if (p.local) {
+    p.off_ctrl = take(4);  // the validation count
+  } else if (p.literal) {
     // counts and both traverse maps are contiguous: one zero fill clears
     // them; the chunk sums are written whole
     p.scan_chunks = (p.literal_cells + kBigScanChunk - 1) / kBigScanChunk;

@@ -71,6 +71,7 @@ struct Plan {
   KeyInfo key;
   bool pairs = false;
   bool literal = false;      // keys only, whole space counted at once
+  bool local = false;        // short array: one workgroup sorts it on chip
   uint32_t literal_cells = 0;
   uint32_t map_rows = 1, map_inner = 0;  // literal: traverse-map rows and cells per row
   bool prescanned = false;   // passes without look-back
@@ -116,5 +117,7 @@ constexpr uint32_t kScanChunk = kScanBlock * kScanItems;
 constexpr uint32_t kBigScanItems = 16;
 constexpr uint32_t kBigScanChunk = kScanBlock * kBigScanItems;
 constexpr uint32_t kLiteralMaxCells = 1u << 24;
+// Longest array one workgroup sorts whole on chip (256 threads x 16 keys).
+constexpr uint64_t kLocalMaxN = 4096;
 
 }  // namespace rs

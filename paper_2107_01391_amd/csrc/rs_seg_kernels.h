@@ -115,6 +115,7 @@ struct SmallParams {
   const uint64_t *seg_lo, *seg_hi;
   const uint32_t *small_ids;
   const uint32_t *nsmall;
+  uint64_t single_n;  // rs_local_sort without small_ids: the one array [0, single_n)
 };
 
 // Sorts whole arrays of at most BLOCK*KPT keys, one per workgroup iteration.
@@ -215,11 +216,15 @@ __global__ __launch_bounds__(BLOCK, 4) void rs_local_sort(const SmallParams<Digi
   __shared__ uint32_t wsum[BLOCK / kWave];
   const uint32_t t = threadIdx.x, lane = t % kWave, wave = t / kWave;
   const uint32_t first = t * KPT;
-  const uint32_t nsmall = *sp.nsmall;
+  const uint32_t nsmall = sp.small_ids ? *sp.nsmall : 1u;
   for (uint32_t idx = blockIdx.x; idx < nsmall; idx += gridDim.x) {
-    const uint32_t sid = sp.small_ids[idx];
-    const uint64_t b = sp.seg_lo[sid];
-    const uint32_t len = (uint32_t)(sp.seg_hi[sid] - b);
+    uint64_t b = 0;
+    uint32_t len = (uint32_t)sp.single_n;
+    if (sp.small_ids) {
+      const uint32_t sid = sp.small_ids[idx];
+      b = sp.seg_lo[sid];
+      len = (uint32_t)(sp.seg_hi[sid] - b);
+    }
     const uint32_t nv = first >= len ? 0u : (len - first < (uint32_t)KPT ? len - first : (uint32_t)KPT);
     // coalesced loads into LDS, then each thread takes its own run
 #pragma unroll

@@ -27,6 +27,7 @@
 #include "rs_internal.h"
 #include "rs_kernels.h"
 #include "rs_passes.h"
+#include "rs_seg_kernels.h"
 
 namespace rs {
 
@@ -326,9 +327,47 @@ rs_status check_alignment(const KeyInfo &k, const void *ki, const void *ko, cons
   return RS_OK;
 }
 
+// A short array (at most kLocalMaxN keys): one workgroup loads it into LDS,
+// runs every pass there and writes it back, so keys_out may equal keys_in.
+template <typename K, class Digit>
+static rs_status run_local(const Plan &pl, const Digit *digits, const void *ki, void *ko, const uint32_t *vi,
+                           uint32_t *vo, hipStream_t s) {
+  static_assert(256 * 16 == kLocalMaxN, "one tile of rs_local_sort");
+  if (pl.n > kLocalMaxN) return fail(RS_ERR_UNSUPPORTED, "array too long for one workgroup");
+  SmallParams<Digit> sp;
+  memset(&sp, 0, sizeof sp);
+  for (uint32_t i = 0; i < pl.npasses; ++i) {
+    sp.digit[i] = digits[i];
+    sp.pass_cells[i] = pl.pass_cells[i];
+  }
+  sp.npasses = pl.npasses;
+  sp.single_n = pl.n;
+  if (vi)
+    RS_TIMED("rs_small_sort", s, hipLaunchKernelGGL((rs_local_sort<K, Digit, 256, 16, true>), dim3(1), dim3(256), 0, s,
+                                                    sp, (const K *)ki, (K *)ko, vi, vo));
+  else
+    RS_TIMED("rs_small_sort", s, hipLaunchKernelGGL((rs_local_sort<K, Digit, 256, 16, false>), dim3(1), dim3(256), 0,
+                                                    s, sp, (const K *)ki, (K *)ko, nullptr, nullptr));
+  return check_launch("rs_local_sort");
+}
+
 rs_status run_plan(const Plan &pl, const void *ki, void *ko, const uint32_t *vi, uint32_t *vo, void *tmp,
                    hipStream_t s) {
   if (pl.n == 0) return RS_OK;
+  if (pl.local) {
+    switch (pl.mode) {
+    case kModePow2:
+      if (pl.key.key_bytes == 4) return run_local<uint32_t, DigitPow2>(pl, pl.p2, ki, ko, vi, vo, s);
+      return run_local<uint64_t, DigitPow2>(pl, pl.p2, ki, ko, vi, vo, s);
+    case kModeDiv32:
+      if (pl.key.key_bytes == 4) return run_local<uint32_t, DigitDiv32>(pl, pl.d32, ki, ko, vi, vo, s);
+      return run_local<uint64_t, DigitDiv32>(pl, pl.d32, ki, ko, vi, vo, s);
+    case kModeDiv64:
+      return run_local<uint64_t, DigitDiv64>(pl, pl.d64, ki, ko, vi, vo, s);
+    default:
+      return fail(RS_ERR_BAD_DESC, "short arrays of this key kind have no on-chip sort");
+    }
+  }
   if (pl.literal) return run_literal(pl, ki, ko, tmp, s);
   const uint32_t kb = pl.key.key_bytes;
   switch (pl.mode) {

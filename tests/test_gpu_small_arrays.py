@@ -1,9 +1,10 @@
-"""Small arrays of the batched form (up to 4096 keys), sorted whole on chip:
+"""Arrays of up to 4096 keys, sorted whole on chip.  In the batched form:
 rs_local_sort (4-bit sub-passes over each cell index, for plans of two or
-more passes) and rs_small_sort (one pass, ballot ranking).  Every array is
-compared with the oracle's sort of that array alone, at every length class
-a tile meets: empty, single, one short of / exactly / one past a 16-key run,
-ragged, and the 4096-key maximum."""
+more passes) and rs_small_sort (one pass, ballot ranking).  A single short
+array given to rs_sort_pairs / rs_sort_keys: one workgroup of rs_local_sort.
+Every array is compared with the oracle's sort of that array alone, at every
+length class a tile meets: empty, single, one short of / exactly / one past
+a 16-key run, ragged, and the 4096-key maximum."""
 from __future__ import annotations
 
 import sys
@@ -14,7 +15,7 @@ import pytest
 import oracle
 from paper_2107_01391_amd import _binding as B
 from paper_2107_01391_amd import api, workloads
-from tests.gpu_helpers import assert_same, fast_groups, key_dtype, key_shape
+from tests.gpu_helpers import assert_same, fast_groups, gpu_sort, key_dtype, key_shape
 
 pytestmark = pytest.mark.gpu
 
@@ -112,3 +113,23 @@ def test_many_small_arrays_log_uniform():
     gv = api.to_host(vo, np.uint32, (total,))
     ok, ov, _ = oracle.sort_segments(keys, vals, offs, kind="u32", base=256, ndims=4, groups=[1, 1, 1, 1])
     assert_same(gk, gv, ok, ov, "3000 log-uniform small arrays")
+
+
+@pytest.mark.parametrize("n", [1, 2, 17, 1000, 4095, 4096, 4097])
+@pytest.mark.parametrize("kind,base,ndims,desc", CASES, ids=[f"{c[0]}-b{c[1]}-n{c[2]}{'-desc' if c[3] else ''}"
+                                                               for c in CASES])
+def test_single_short_array(kind, base, ndims, desc, n):
+    """rs_sort_pairs / rs_sort_keys on one array of at most 4096 keys: one
+    workgroup, every pass on chip (4097 takes the passes), also in place."""
+    _say(f"short array {kind} base {base} ndims {ndims} desc {desc} n {n}")
+    rng = np.random.default_rng(n)
+    keys = _keys(kind, base, ndims, n, rng)
+    keys[: n // 3] = keys[0]
+    vals = rng.permutation(n).astype(np.uint32)
+    groups = fast_groups(kind, base, ndims)
+    ok, ov, _ = oracle.sort(keys, vals, kind=kind, base=base, ndims=ndims, groups=groups, descending=desc)
+    gk, gv = gpu_sort(keys, vals, kind, base, ndims, descending=desc)
+    assert_same(gk, gv, ok, ov, f"pairs n={n}")
+    ok2, _, _ = oracle.sort(keys, None, kind=kind, base=base, ndims=ndims, groups=groups, descending=desc)
+    gk2, _ = gpu_sort(keys, None, kind, base, ndims, in_place=True, descending=desc)
+    assert_same(gk2, None, ok2, None, f"keys in place n={n}")
