@@ -105,11 +105,14 @@ typedef struct rs_key_desc {
 } rs_key_desc;
 
 /* Scratch bytes that rs_sort_keys (with_values = 0) or rs_sort_pairs
- * (with_values = 1) need for n keys of this description.  Writes *bytes. */
+ * (with_values = 1) need for n keys of this description.  Writes *bytes.
+ * Arrays of at most 4096 keys of 4 or 8 bytes are sorted whole in one
+ * workgroup's LDS (every pass on chip, one launch); they need 256 bytes. */
 rs_status rs_temp_bytes(const rs_key_desc *desc, uint64_t n, int with_values, size_t *bytes);
 
 /* Sorts n keys.  Keys only: when the whole count space is small (b^N cells,
- * at most a few cells per key) this runs the paper's literal form: count
+ * at most a few cells per key, and more than 4096 keys) this runs the
+ * paper's literal form: count
  * every cell, scan the counts in lexicographic order, and write each cell's
  * count copies of the key rebuilt from the cell's coordinates (eq. (16));
  * otherwise it runs the grouped passes of rs_sort_pairs without payload.

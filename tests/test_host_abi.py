@@ -253,3 +253,21 @@ def test_signed_kinds_need_a_covering_space():
     asc = B.rs_temp_bytes(B.key_desc("u32", base=10, ndims=6), 10**6, False)
     desc = B.rs_temp_bytes(B.key_desc("u32", base=10, ndims=6, descending=True), 10**6, False)
     assert asc >= 8 * 10**6 and desc != asc
+
+
+def test_short_arrays_plan_one_workgroup():
+    """Arrays of at most 4096 four- or eight-byte keys are sorted whole on
+    chip: their scratch is one small control block, independent of n; one
+    key more takes the passes and their alternate arrays.  16-byte strings
+    always take the passes."""
+    for kind, base, ndims in [("u32", 256, 4), ("u64", 10, 15), ("fixed_i64", 10, 9), ("i32", 256, 4),
+                              ("i64", 16, 16), ("u32", 10, 6)]:
+        d = B.key_desc(kind, base=base, ndims=ndims)
+        for pairs in (True, False):
+            short = {B.rs_temp_bytes(d, n, pairs) for n in (1, 17, 4095, 4096)}
+            assert short == {256}, (kind, pairs, short)
+            assert B.rs_temp_bytes(d, 4097, pairs) > 4097 * 4, (kind, pairs)
+        dd = B.key_desc(kind, base=base, ndims=ndims, descending=True)
+        assert B.rs_temp_bytes(dd, 4096, True) == 256
+    s = B.key_desc("str", base=27, ndims=16)
+    assert B.rs_temp_bytes(s, 100, True) > 100 * 16
