@@ -343,8 +343,10 @@ struct rs_server {
         cv_done.notify_all();
         cv_dispatch.notify_one();
       } else {
+        // launches are in flight: poll again at once (a timed sleep lasts
+        // tens of microseconds past its request, all of it added latency)
         lk.unlock();
-        std::this_thread::sleep_for(std::chrono::microseconds(20));
+        std::this_thread::yield();
         lk.lock();
       }
     }

@@ -175,11 +175,13 @@ def run_trace(server: Server, pool, gaps_s: np.ndarray, sizes: np.ndarray, warmu
             reap(500)
         else:
             left_us = int((arrivals[i] - Server.clock()) / 1e3)
-            if left_us > 0:
+            # a sleep or a timed wait overshoots by tens of microseconds:
+            # stop short of the arrival and spin the rest
+            if left_us > 200:
                 if outstanding:
-                    reap(min(left_us, 500))
+                    reap(min(left_us - 150, 500))
                 else:
-                    time.sleep(min(left_us, 500) / 1e6)
+                    time.sleep(min(left_us - 150, 500) / 1e6)
     st = server.stats()
     st["gkeys_per_s"] = st["keys_sorted"] / (st["span_ms"] / 1e3) / 1e9 if st["span_ms"] > 0 else 0.0
     return st
