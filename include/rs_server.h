@@ -31,7 +31,9 @@
  *
  * Completion.  A completion thread marks a request done once its launch's
  * event has completed.  The request's latency runs from its arrival (given
- * at submit, or the submit time) to that moment.
+ * at submit, or the submit time) to that moment.  While launches are in
+ * flight the thread polls their events without sleeping (it occupies one
+ * host core then); with none in flight it blocks.
  *
  * Each request's result is the stable sort of its own keys.  It is the same
  * whichever other requests share its launch.
