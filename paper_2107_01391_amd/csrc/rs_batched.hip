@@ -138,6 +138,9 @@ rs_status rs_sort_batched(const rs_key_desc *desc, const void *keys_in, void *ke
     if ((st = validate_offsets(d_seg_offsets, nseg, total, tmp, s)) != RS_OK) return st;
     if ((st = validate_keys(p, keys_in, total, tmp, s)) != RS_OK) return st;
   }
+  // when the arrays are short on average, most are sorted on chip and the
+  // mean is their typical length
+  if (total / nseg <= p.seg.small_max) p.seg.small_len = total / nseg;
   // array i is [offsets[i], offsets[i + 1])
   return batched_run(p, keys_in, keys_out, vals_in, vals_out, d_seg_offsets, d_seg_offsets + 1, tmp, s);
 }

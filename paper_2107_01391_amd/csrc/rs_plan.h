@@ -59,6 +59,7 @@ struct SegLayout {
   uint32_t small_grid = 1;
   bool own_alt = false;
   bool any_large = true;  // false when the caller knows every array is small: no passes are launched
+  uint64_t small_len = 0;  // typical length of the small arrays when the caller knows it, else 0
   size_t off_alt_keys = 0, off_alt_vals = 0;
   size_t off_ctrl = 0;  // nlarge, nsmall, tiles in use
   size_t off_large_ids = 0, off_tile_base = 0, off_small_ids = 0;

@@ -23,6 +23,9 @@ namespace rs {
 // of plan p (least significant first) into the same positions of keys_out.
 // The arrays lie within the first L.extent elements and do not overlap;
 // alt_* are scratch arrays of L.extent elements.
+// Typical small-array length up to which rs_local_sort is used.
+constexpr uint64_t kLocalSortMaxLen = 2048;
+
 template <typename K, class Digit, int BITS>
 rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, const void *keys_in,
                         void *keys_out, const uint32_t *vals_in, uint32_t *vals_out, void *alt_keys,
@@ -66,9 +69,11 @@ rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, 
   sp.nsmall = nsmall;
   bool launched = false;
   if constexpr (sizeof(K) <= 8) {
-    // several passes: 4-bit sub-passes with per-thread counts issue fewer
-    // instructions per key than ballot ranking; one pass is cheaper ranked
-    if (P >= 2) {
+    // several passes over short arrays: 4-bit sub-passes with per-thread
+    // counts; one pass, or arrays near the 4096-key limit, are cheaper
+    // ranked by ballots (whose per-pass cell scan costs the same for any
+    // length)
+    if (P >= 2 && (L.small_len == 0 || L.small_len <= kLocalSortMaxLen)) {
       if (pairs)
         RS_TIMED("rs_small_sort", stream,
                  hipLaunchKernelGGL((rs_local_sort<K, Digit, 256, 16, true>), dim3(L.small_grid), dim3(256), 0,

@@ -240,17 +240,23 @@ struct rs_server {
     rs_status st = make_batched(&desc, 1, cfg.capacity, (uint32_t)spans.size(), pairs, &p, &why);
     if (st != RS_OK) return fail(st, why);
     uint64_t *lo = staging[i], *hi = staging[i] + batch_cap(&cfg);
-    uint64_t large = 0;
+    uint64_t large = 0, small = 0, nsmall = 0;
     for (size_t j = 0; j < spans.size(); ++j) {
       lo[j] = spans[j].offset;
       hi[j] = spans[j].offset + spans[j].n;
-      if (spans[j].n > p.seg.small_max) large += spans[j].n;
+      if (spans[j].n > p.seg.small_max) {
+        large += spans[j].n;
+      } else {
+        small += spans[j].n;
+        ++nsmall;
+      }
     }
     if (large > 1) {
       st = make_batched(&desc, large, cfg.capacity, (uint32_t)spans.size(), pairs, &p, &why);
       if (st != RS_OK) return fail(st, why);
     }
     p.seg.any_large = large > 0;
+    p.seg.small_len = nsmall ? small / nsmall : 0;
     if (p.total > w.tmp_bytes) return fail(RS_ERR_TMP_TOO_SMALL, "server scratch below this batch's plan");
     const size_t nb = spans.size() * 8;
     uint64_t *dlo = (uint64_t *)(work + w.lo_off), *dhi = (uint64_t *)(work + w.hi_off);

@@ -99,6 +99,33 @@ def test_small_arrays(kind, base, ndims, desc, pairs):
     assert_same(gk, gv, ok, ov, f"{kind} base {base} ndims {ndims} desc {desc}")
 
 
+LONG_LENGTHS = [4096, 4000, 3001, 2049, 4095, 1, 4096, 2500, 0, 3333]
+
+
+@pytest.mark.parametrize("kind,base,ndims,desc", CASES, ids=[f"{c[0]}-b{c[1]}-n{c[2]}{'-desc' if c[3] else ''}"
+                                                               for c in CASES])
+def test_small_arrays_near_the_limit(kind, base, ndims, desc):
+    """Arrays averaging over 2048 keys take the ballot-ranked kernel for
+    every plan (the sub-pass kernel serves shorter ones)."""
+    import torch
+    _say(f"small arrays near 4096 {kind} base {base} ndims {ndims} desc {desc}")
+    rng = np.random.default_rng(20210712)
+    offs = _offsets(LONG_LENGTHS)
+    total = int(offs[-1])
+    keys = _keys(kind, base, ndims, total, rng)
+    keys[int(offs[2]):int(offs[2]) + 2000] = keys[int(offs[2])]
+    vals = rng.permutation(total).astype(np.uint32)
+    d = B.key_desc(kind, base=base, ndims=ndims, descending=desc)
+    ko, vo = api.sort_batched(d, api.to_device(keys), api.to_device(vals), api.to_device(offs), len(LONG_LENGTHS),
+                              total)
+    torch.cuda.synchronize()
+    gk = api.to_host(ko, key_dtype(kind), key_shape(kind, total))
+    gv = api.to_host(vo, np.uint32, (total,))
+    ok, ov, _ = oracle.sort_segments(keys, vals, offs, kind=kind, base=base, ndims=ndims,
+                                     groups=fast_groups(kind, base, ndims), descending=desc)
+    assert_same(gk, gv, ok, ov, f"{kind} base {base} ndims {ndims} desc {desc}")
+
+
 def test_many_small_arrays_log_uniform():
     """Thousands of arrays of 1..4096 keys, every workgroup sorting many."""
     import torch
