@@ -429,11 +429,6 @@ template <int BITS, int KPT, typename K, class Digit>
 __device__ __forceinline__ void wave_rank(const Digit &digit, const K (&k)[KPT], uint32_t nvalid, uint32_t *my,
                                           uint32_t (&dg)[KPT], uint32_t (&rk)[KPT]) {
   const uint32_t lane = lane_id();
-  if (nvalid == 0) {  // uniform: a wave past the end of a short array ranks nothing
-#pragma unroll
-    for (int r = 0; r < KPT; ++r) dg[r] = rk[r] = 0;
-    return;
-  }
 #pragma unroll
   for (int r = 0; r < KPT; ++r) {
     const bool valid = (uint32_t)r * kWave + lane < nvalid;

@@ -157,7 +157,12 @@ __global__ __launch_bounds__(BLOCK) void rs_small_sort(const SmallParams<Digit> 
       for (uint32_t i = t; i < (uint32_t)(WAVES * BINS); i += BLOCK) (&wcnt[0][0])[i] = 0;
       __syncthreads();
       uint32_t dg[KPT], rk[KPT];
-      wave_rank<BITS, KPT>(sp.digit[pass], k, nvalid, wcnt[wave], dg, rk);
+      if (nvalid) {
+        wave_rank<BITS, KPT>(sp.digit[pass], k, nvalid, wcnt[wave], dg, rk);
+      } else {  // uniform: a wave past the end of a short array ranks nothing
+#pragma unroll
+        for (int r = 0; r < KPT; ++r) dg[r] = rk[r] = 0;
+      }
       __syncthreads();
       uint32_t tot[CPT];
       cell_totals<BLOCK, WAVES, BINS, CPT>(wcnt, tstart, cells, tot);
