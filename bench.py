@@ -43,9 +43,9 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n: int):
-    """HBM bytes per rs_rank_scatter launch from the committed PMC summary,
-    or None when it is missing, for another size, or the kernel changed."""
+def pmc_summary(n: int):
+    """The committed PMC summary, or None when it is missing, for another
+    size, or the kernels changed since the counters were taken."""
     try:
         with open(PMC_FILE) as f:
             pmc = json.load(f)
@@ -53,7 +53,23 @@ def measured_traffic(n: int):
         return None
     if pmc.get("kernel_source_sha") != kernel_source_sha() or pmc.get("n") != n:
         return None
-    return pmc.get("hbm_bytes_per_launch")
+    return pmc
+
+
+def measured_traffic(n: int):
+    """HBM bytes per rs_rank_scatter launch (PMC), or None."""
+    pmc = pmc_summary(n)
+    return pmc.get("hbm_bytes_per_launch") if pmc else None
+
+
+def measured_pass_bytes(n: int):
+    """HBM bytes of one whole pass (count, scan, scatter; PMC), or None."""
+    pmc = pmc_summary(n)
+    try:
+        return (pmc["hbm_bytes_per_launch"] + pmc["rs_tile_histogram"]["bytes_scaled"]
+                + pmc["rs_cell_scan"]["bytes_scaled"])
+    except (TypeError, KeyError):
+        return None
 
 
 def cpu_baseline(w, sample: int) -> dict:
@@ -268,6 +284,12 @@ def main() -> int:
              "planned_GBps": round(planned * n / (ms_per_step / 1e3) / 1e9, 1),
              "planned_frac_of_peak": round(planned * n / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
              "wall_ms_per_step": round(wall_ms_per_step, 4), "kernel_ms_per_step": kernel_ms}
+    pass_bytes = measured_pass_bytes(n)
+    # counter-measured bytes of every kernel of the sort over its time: the
+    # whole sort's share of the HBM peak (null when the counters are stale)
+    whole["measured_bytes_per_step"] = pass_bytes * passes if pass_bytes else None
+    whole["measured_frac_of_peak"] = (round(pass_bytes * passes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                      if pass_bytes else None)
     del keys_out, vals_out, tmp
     torch.cuda.empty_cache()
 
