@@ -9,11 +9,12 @@
 //   rs_small_sort     one workgroup per small array, every pass in LDS: count
 //                     the cells, scan them, place the keys -- the hashing and
 //                     extraction cycles of Sections 3.1 and 3.2 on chip
-//                     (16-byte keys)
+//                     (ballot ranking; 16-byte keys, one-pass plans, and
+//                     arrays near the 4096-key limit)
 //   rs_local_sort     the same for 4- and 8-byte keys, by 4-bit sub-passes
-//                     over each cell index with per-thread counts (used when
-//                     there are two or more passes: one 8-bit pass is
-//                     cheaper as the ballot-ranked rs_small_sort)
+//                     over each cell index with per-thread counts (plans of
+//                     two or more passes over short arrays, and a single
+//                     short array given to rs_sort_pairs / rs_sort_keys)
 //   (the large arrays' passes are rs_tile_histogram, the cell scan and
 //   rs_rank_scatter<..., kPrescannedSeg>)
 #pragma once
