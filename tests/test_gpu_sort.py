@@ -367,3 +367,31 @@ def test_prescanned_digit_widths(prescanned, monkeypatch, tile_block, base, ndim
     gk, gv = gpu_sort(w.keys, w.vals, "u32", base, ndims)
     ok, ov = oracle_sort(w.keys, w.vals, "u32", base, ndims)
     assert_same(gk, gv, ok, ov)
+
+
+@pytest.mark.parametrize("n", [100_003, 3_500_001], ids=["chained", "prescanned"])
+@pytest.mark.parametrize("pattern", ["sorted", "reverse", "all_equal", "two_values"])
+def test_ordered_and_degenerate_inputs(pattern, n):
+    """Inputs whose stable sort is known in closed form: already sorted
+    (identity), reverse sorted with distinct keys (reversal), all keys equal
+    (identity: every tie keeps input order), two alternating values (evens
+    then odds).  Every key of a tile in one cell is the worst case of the
+    count tables' atomics."""
+    _say(f"ordered input {pattern} n={n}")
+    idx = np.arange(n, dtype=np.uint64)
+    if pattern == "sorted":
+        keys = (idx * 61).astype(np.uint32)
+        want = idx
+    elif pattern == "reverse":
+        keys = ((n - idx) * 61).astype(np.uint32)
+        want = idx[::-1]
+    elif pattern == "all_equal":
+        keys = np.full(n, 0xDEADBEEF, np.uint32)
+        want = idx
+    else:
+        keys = np.where(idx % 2 == 0, 7, 0x7000000).astype(np.uint32)
+        want = np.concatenate([idx[0::2], idx[1::2]])
+    vals = idx.astype(np.uint32)
+    gk, gv = gpu_sort(keys, vals, "u32", 256, 4)
+    assert np.array_equal(gv, want.astype(np.uint32)), pattern
+    assert np.array_equal(gk, keys[want.astype(np.int64)]), pattern
