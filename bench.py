@@ -209,8 +209,9 @@ def main() -> int:
                     help="also run a plain 1 GiB read + 1 GiB write kernel (scale reference for PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the sort runs on a single MI355X; a run on more GPUs is not part "
-              "of this build (see the sharding notes in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the sort runs on a single MI355X. Several GPUs would split the "
+              "count space by the leading digit group and exchange pairs with one all-to-all; that is not "
+              "implemented, so only --gpus 1 runs", file=sys.stderr)
         return 2
 
     import torch
