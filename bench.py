@@ -97,6 +97,22 @@ def check_sorted(torch, keys_in, keys_out, vals_out, n):
     return ok
 
 
+def oracle_digest_match(keys_out, vals_out, n: int):
+    """SHA-256 of the output key and value bytes against the digests the
+    oracle wrote for the same seeded workload (tests/golden/digests.json);
+    None when none is stored for this size."""
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "digests.json")) as f:
+            rec = json.load(f)["workloads"]["uniform_u32_pairs"]
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("n") != n:
+        return None
+    hk = hashlib.sha256(keys_out[: 4 * n].cpu().numpy().data).hexdigest()
+    hv = hashlib.sha256(vals_out[: 4 * n].cpu().numpy().data).hexdigest()
+    return hk == rec["keys_sha256"] and hv == rec["vals_sha256"]
+
+
 def batched_vs_per_array(torch, B, workloads, count: int) -> dict:
     """`count` arrays with log-uniform sizes in [2^10, 2^22] (the seeded size
     law), uniform u32 keys and local-index payloads drawn on the device.
@@ -291,6 +307,10 @@ def main() -> int:
     whole["measured_bytes_per_step"] = pass_bytes * passes if pass_bytes else None
     whole["measured_frac_of_peak"] = (round(pass_bytes * passes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
                                       if pass_bytes else None)
+    # the timed steps' output, byte for byte, against the oracle's digest
+    digest_ok = oracle_digest_match(keys_out, vals_out, n)
+    print(f"[bench] oracle digest {'match' if digest_ok else ('MISMATCH' if digest_ok is False else 'not stored')}",
+          file=sys.stderr, flush=True)
     del keys_out, vals_out, tmp
     torch.cuda.empty_cache()
 
@@ -324,7 +344,7 @@ def main() -> int:
                                "base 256, 4 dimensions, stable ascending (rs_sort_pairs)",
                    "n": n, "passes": passes},
         "roofline": roofline, "whole_sort": whole, "cpu_baseline": cpu, "batched_vs_per_array": batched,
-        "served": served, "output_check": ok,
+        "served": served, "output_check": ok, "oracle_digest_match": digest_ok,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(line), flush=True)
