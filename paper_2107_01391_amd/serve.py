@@ -188,7 +188,7 @@ def run_trace(server: Server, pool, gaps_s: np.ndarray, sizes: np.ndarray, warmu
 
 
 def sweep(rates, requests: int, warmup: int, capacity: int, streams: int, seed: int = 20210708,
-          verbose: bool = True) -> list[dict]:
+          verbose: bool = True, min_batch: int = 0) -> list[dict]:
     """The same seeded traces (sizes log-uniform in [2^10, 2^22], Poisson
     arrivals at each rate; rate 0 = as fast as admission allows) through a
     per-request server and a batched server."""
@@ -198,7 +198,7 @@ def sweep(rates, requests: int, warmup: int, capacity: int, streams: int, seed: 
     sizes_all = workloads.batched_sizes(requests + warmup, seed_extra=[seed])
     pool = make_pool(32, np.array([int(sizes_all.max())]), seed)  # entries long enough for every size
     for mode, name in ((B.RS_SERVE_PER_REQUEST, "per_request"), (B.RS_SERVE_BATCHED, "batched")):
-        srv = Server(desc, capacity, max_slots=512, streams=streams, mode=mode)
+        srv = Server(desc, capacity, max_slots=512, streams=streams, mode=mode, min_batch=min_batch)
         try:
             for rate in rates:
                 rng = np.random.default_rng([seed, int(rate)])
@@ -247,8 +247,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--capacity", type=int, default=1 << 29)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--min-batch", type=int, default=0, help="batched mode: fewest queued requests batched (0 = 4)")
     a = ap.parse_args()
-    rows = sweep([float(r) for r in a.rates.split(",")], a.requests, a.warmup, a.capacity, a.streams)
+    rows = sweep([float(r) for r in a.rates.split(",")], a.requests, a.warmup, a.capacity, a.streams,
+                 min_batch=a.min_batch)
     print(json.dumps({"gate": gate(rows)}), flush=True)
 
 
