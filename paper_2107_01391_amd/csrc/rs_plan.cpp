@@ -262,6 +262,10 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
   // keys per thread sized so that the LDS staging of one tile stays at
   // 32 KiB per 256 threads for wide keys
   p.prescanned = !p.literal && !p.local && n >= tune.prescan_min_n;
+  // 8-byte keys whose space fits 32 bits (unsigned, or fixed point below
+  // 10^9): narrowed once, sorted as 32-bit words, widened at the end
+  p.narrow = p.prescanned && k.key_bytes == 8 && !k.is_signed && k.space && k.space <= (1ull << 32) &&
+             p.npasses >= 2 && p.mode != kModeDiv64;
   p.block = p.prescanned ? prescan_block(tune, k.key_bytes, p.bits) : 256;
   p.kpt = k.key_bytes >= 16 ? 8 : 16;
   p.tile = p.block * p.kpt;
@@ -296,7 +300,8 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     p.off_sums = take((size_t)p.scan_chunks * 4);
     p.off_starts = take((size_t)p.literal_cells * 4);
   } else if (p.prescanned) {
-    p.off_keys_alt = take((size_t)n * k.key_bytes);
+    // narrowed keys: two 32-bit arrays, the second 256-byte aligned
+    p.off_keys_alt = take((size_t)n * k.key_bytes + (p.narrow ? 256 : 0));
     if (pairs) p.off_vals_alt = take((size_t)n * 4);
     const uint64_t entries = (uint64_t)p.bins * p.ntiles;
     p.scan_chunks = (uint32_t)((entries + kBigScanChunk - 1) / kBigScanChunk);

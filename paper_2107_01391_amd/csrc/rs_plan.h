@@ -73,6 +73,7 @@ struct Plan {
   bool pairs = false;
   bool literal = false;      // keys only, whole space counted at once
   bool local = false;        // short array: one workgroup sorts it on chip
+  bool narrow = false;       // 8-byte keys below 2^32: the passes move them as 32-bit words
   uint32_t literal_cells = 0;
   uint32_t map_rows = 1, map_inner = 0;  // literal: traverse-map rows and cells per row
   bool prescanned = false;   // passes without look-back

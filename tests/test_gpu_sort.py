@@ -395,3 +395,24 @@ def test_ordered_and_degenerate_inputs(pattern, n):
     gk, gv = gpu_sort(keys, vals, "u32", 256, 4)
     assert np.array_equal(gv, want.astype(np.uint32)), pattern
     assert np.array_equal(gk, keys[want.astype(np.int64)]), pattern
+
+
+@pytest.mark.parametrize("kind,base,ndims", [("u64", 256, 4), ("u64", 10, 9), ("fixed_i64", 10, 9)],
+                         ids=["u64-b256-even", "u64-b10-odd", "fixed-odd"])
+@pytest.mark.parametrize("form", ["pairs", "keys_in_place", "pairs_in_place_desc"])
+def test_narrowed_eight_byte_keys(kind, base, ndims, form):
+    """8-byte keys whose space fits 32 bits, at a size that takes the
+    prescanned passes: narrowed to 32-bit words for the passes and widened
+    at the end (even and odd pass counts, in place, descending)."""
+    n = 3_300_007
+    _say(f"narrowed {kind} base {base} ndims {ndims} {form} n={n}")
+    rng = np.random.default_rng(n + ndims)
+    space = base ** ndims
+    keys = rng.integers(0, space, n, dtype=np.int64 if kind == "fixed_i64" else np.uint64)
+    keys[::7] = keys[3]  # ties
+    keys[0], keys[1] = 0, space - 1
+    desc = form.endswith("desc")
+    vals = None if form.startswith("keys") else rng.permutation(n).astype(np.uint32)
+    gk, gv = gpu_sort(keys, vals, kind, base, ndims, in_place="in_place" in form, descending=desc)
+    ok, ov = oracle_sort(keys, vals, kind, base, ndims, descending=desc)
+    assert_same(gk, gv, ok, ov, f"{kind} {form}")
