@@ -43,7 +43,9 @@
  *     whose spaces cover the type).  With
  *     RS_FLAG_VALIDATE the library checks this first (a synchronous extra
  *     read) and returns RS_ERR_KEY_RANGE; without it, out-of-space keys give
- *     an unspecified order (never a fault).
+ *     an unspecified order (never a fault).  8-byte keys of a space that
+ *     fits 32 bits are carried as 32-bit words through large sorts, so an
+ *     out-of-space one may also come back with only its low 32 bits.
  *   - No exception crosses the ABI and nothing aborts.  rs_last_error()
  *     returns a thread-local description of the last failure.
  */
