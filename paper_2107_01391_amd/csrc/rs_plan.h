@@ -42,7 +42,7 @@ struct KeyInfo {
 struct Tuning {
   uint32_t digit_bits = 8;       // target width of a pass (power-of-two bases)
   uint32_t max_cells = 256;      // largest count space of one pass (other bases; strings: 729)
-  uint64_t prescan_min_n = 3ull << 20;  // single arrays from this size use prescanned passes
+  uint64_t prescan_min_n = 1ull << 21;  // single arrays from this size use prescanned passes
   uint32_t tile_block = 512;            // threads per tile of prescanned passes (256 or 512)
 };
 
