@@ -117,11 +117,15 @@ def test_graph_sort_replays_new_data(monkeypatch, n, prescan):
         g.close()
 
 
-def test_graph_keys_only_in_place_odd_passes():
-    """Keys only, in place, three passes (odd): the graph holds the copy
-    kernel that starts an odd pass count in place."""
+@pytest.mark.parametrize("prescan", [False, True], ids=["chained", "prescanned_narrowed"])
+def test_graph_keys_only_in_place_odd_passes(monkeypatch, prescan):
+    """Keys only, in place, an odd pass count: chained, the graph holds the
+    copy kernel that starts an odd pass count in place; prescanned, the
+    fixed-point keys (below 10^9) are narrowed to 32-bit words, sorted and
+    widened back in place."""
     import torch
-    _say("graph keys only in place")
+    monkeypatch.setenv("RS_PRESCAN_MIN_N", "1" if prescan else str(1 << 40))
+    _say(f"graph keys only in place prescan={prescan}")
     n = 200_001
     d = B.key_desc("fixed_i64", base=10, ndims=9, frac_digits=3)
     k = api.empty_device(8 * n)
