@@ -30,7 +30,8 @@ class Server:
         self.desc = desc
         self.cfg = B.ServerConfig(capacity, max_slots, max_batch, streams, mode, int(bool(with_values)), min_batch,
                                   batch_max_n)
-        kb = {0: 4, 1: 8, 2: 8, 3: 16}[desc.kind]
+        kb = {B.RS_KEY_U32: 4, B.RS_KEY_U64: 8, B.RS_KEY_FIXED_I64: 8, B.RS_KEY_STR: desc.str_width or 16,
+              B.RS_KEY_I32: 4, B.RS_KEY_I64: 8}[desc.kind]
         self.kb = kb
         dev = "cuda"
         self.keys_in = torch.empty(capacity * kb, dtype=torch.uint8, device=dev)

@@ -139,6 +139,33 @@ def test_fixed_point_keys_only_server():
 
 
 @pytest.mark.parametrize("mode", [B.RS_SERVE_BATCHED, B.RS_SERVE_PER_REQUEST])
+def test_signed_descending_server(mode):
+    """Signed 32-bit keys in descending order with values, submitted
+    together: each result equals the oracle's sort of that request."""
+    _say(f"server signed descending mode={mode}")
+    desc = B.key_desc("i32", base=256, ndims=4, descending=True)
+    rng = np.random.default_rng(77)
+    sizes = [1, 4096, 4097, 30_000, 250_000, 3, 70_001]
+    keys = [rng.integers(-2**31, 2**31, n, dtype=np.int64).astype(np.int32) for n in sizes]
+    for k in keys[3:4]:
+        k[::5] = k[0]  # ties
+    vals = [rng.permutation(n).astype(np.uint32) for n in sizes]
+    srv = Server(desc, capacity=400_000, max_slots=16, streams=2, mode=mode)
+    try:
+        tickets = [srv.submit(api.to_device(k), api.to_device(v), k.shape[0]) for k, v in zip(keys, vals)]
+        for t in tickets:
+            srv.wait(t)
+        for t, k, v in zip(tickets, keys, vals):
+            rk, rv = srv.result(t)
+            ok, ov = oracle_sort(k, v, "i32", 256, 4, descending=True)
+            assert np.array_equal(rk.cpu().numpy().view(np.int32), ok)
+            assert np.array_equal(rv.cpu().numpy().view(np.uint32), ov)
+            srv.release(t)
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("mode", [B.RS_SERVE_BATCHED, B.RS_SERVE_PER_REQUEST])
 def test_short_poisson_trace(mode):
     _say(f"server trace mode={mode}")
     desc = B.key_desc("u32", base=256, ndims=4)
