@@ -150,9 +150,11 @@ rs_status rs_batched_temp_bytes(const rs_key_desc *desc, uint64_t total, uint32_
  * all arrays sharing every launch.  The launch shapes depend only on
  * (total, nseg), so a captured hipGraph can be replayed for any offsets with
  * the same (total, nseg).  Every array must hold at most RS_MAX_ELEMENTS
- * keys; total must be below 2^40.  Offsets that break these rules give
- * undefined results (reads outside keys_in); with RS_FLAG_VALIDATE they are
- * checked first and give RS_ERR_BAD_DESC. */
+ * keys; total must be below 2^40.  Offsets that break these rules give an
+ * unspecified order and unspecified contents of keys_out / vals_out, but no
+ * access outside the buffers: every array's bounds are clamped to
+ * [0, total) and RS_MAX_ELEMENTS keys on the device before use.  With
+ * RS_FLAG_VALIDATE they are checked first and give RS_ERR_BAD_DESC. */
 rs_status rs_sort_batched(const rs_key_desc *desc, const void *keys_in, void *keys_out, const uint32_t *vals_in,
                           uint32_t *vals_out, const uint64_t *d_seg_offsets, uint32_t nseg, uint64_t total, void *tmp,
                           size_t tmp_bytes, void *stream);

@@ -91,12 +91,16 @@ rs_status rs_server_create(const rs_key_desc *desc, const rs_server_config *cfg,
                            uint32_t *vals_in, uint32_t *vals_out, void *work, size_t work_bytes, rs_server **out);
 
 /* Submits a request of n keys (and values when the server carries them).
- * keys / vals are host or device pointers; the copy into the arena is
- * enqueued on the server's upload stream, so they must stay unchanged until
- * the request is done.  arrival_ns: the request's arrival on rs_server_clock
- * (0 = now).  RS_ERR_BUSY: not admitted now, nothing kept. */
+ * keys / vals are host or device pointers.  The copy into the arena is
+ * enqueued on the server's own upload stream and reads them later, so they
+ * must stay allocated and unchanged until the request is done (a framework
+ * allocator must not hand their memory to another tensor before then).
+ * src_stream (a hipStream_t as void*, NULL = the null stream) is the stream
+ * on which the sources were written: the upload first waits for the work
+ * enqueued there before this call.  arrival_ns: the request's arrival on
+ * rs_server_clock (0 = now).  RS_ERR_BUSY: not admitted now, nothing kept. */
 rs_status rs_server_submit(rs_server *s, const void *keys, const uint32_t *vals, uint64_t n, uint64_t arrival_ns,
-                           uint64_t *ticket);
+                           void *src_stream, uint64_t *ticket);
 
 /* *done = 1 when the request is sorted (or failed: rs_server_wait returns
  * its status). */

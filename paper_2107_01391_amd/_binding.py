@@ -134,7 +134,7 @@ def load_library(path: str | None = None):
     u64p = ctypes.POINTER(u64)
     lib.rs_server_work_bytes.argtypes = [dp, cp, ctypes.POINTER(sz)]
     lib.rs_server_create.argtypes = [dp, cp, vp, vp, vp, vp, vp, sz, gp]
-    lib.rs_server_submit.argtypes = [vp, vp, vp, u64, u64, u64p]
+    lib.rs_server_submit.argtypes = [vp, vp, vp, u64, u64, vp, u64p]
     lib.rs_server_poll.argtypes = [vp, u64, ctypes.POINTER(ci)]
     lib.rs_server_wait.argtypes = [vp, u64]
     lib.rs_server_result.argtypes = [vp, u64, u64p, u64p]

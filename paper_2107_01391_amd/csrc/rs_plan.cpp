@@ -374,6 +374,7 @@ rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint6
   L.off_large_ids = take((size_t)nseg * 4);
   L.off_tile_base = take(((size_t)nseg + 1) * 4);
   L.off_small_ids = take((size_t)nseg * 4);
+  L.off_bounds = take((size_t)nseg * 16);
   L.off_tiles = take(L.tiles_bound * 32);
   const uint64_t entries = (uint64_t)p.bins * L.tiles_bound;
   L.off_table = take(entries * 4);

@@ -63,6 +63,7 @@ struct SegLayout {
   size_t off_alt_keys = 0, off_alt_vals = 0;
   size_t off_ctrl = 0;  // nlarge, nsmall, tiles in use
   size_t off_large_ids = 0, off_tile_base = 0, off_small_ids = 0;
+  size_t off_bounds = 0;  // resolved array bounds: lo[nseg], then hi[nseg]
   size_t off_tiles = 0;  // TileDesc per tile id
   size_t off_table = 0, off_sums = 0;  // per-tile count table and its chunk sums
   size_t bytes = 0;

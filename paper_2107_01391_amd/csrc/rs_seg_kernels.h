@@ -20,23 +20,35 @@
 #pragma once
 
 #include "rs_kernels.h"
+#include "rs_seg_bounds.h"
 
 namespace rs {
 
 // Array s is elements [seg_lo[s], seg_hi[s]).  Offsets of back-to-back
 // arrays are the case seg_hi = seg_lo + 1.
 struct SegPlanParams {
-  const uint64_t *seg_lo, *seg_hi;  // [nseg] each
+  const uint64_t *seg_lo, *seg_hi;  // [nseg] each, as the caller gave them
   uint32_t nseg;
   uint32_t small_max;       // arrays up to this length are sorted on chip
   uint32_t tile;            // keys per tile of the large arrays
+  uint64_t extent;          // every array lies within elements [0, extent)
+  uint32_t tiles_bound;     // large-array tiles the scratch holds
   uint32_t *nlarge, *large_ids, *tile_base;  // tile_base has nlarge + 1 entries
   uint32_t *nsmall, *small_ids;
+  uint64_t *rlo, *rhi;      // [nseg] each: the bounds every later kernel uses
 };
 
-// One workgroup: splits the arrays into small and large ones and numbers
-// the large arrays' tiles array by array (tile_base = tiles of all earlier
-// large arrays).
+// One workgroup: resolves every array's bounds, splits the arrays into
+// small and large ones and numbers the large arrays' tiles array by array
+// (tile_base = tiles of all earlier large arrays).
+//
+// The resolved bounds are the caller's, clamped so that no kernel can
+// reach outside the buffers whatever the offsets hold: each array lies in
+// [0, extent) and holds at most RS_MAX_ELEMENTS keys, and the large arrays
+// number at most tiles_bound tiles (an array past that bound is cut to the
+// tiles left, possibly none).  Valid offsets pass unchanged; invalid ones
+// give an unspecified order, never an access outside keys, values or the
+// scratch.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void rs_seg_plan(const SegPlanParams q) {
   __shared__ uint32_t wsum[BLOCK / kWave];
@@ -45,25 +57,37 @@ __global__ __launch_bounds__(BLOCK) void rs_seg_plan(const SegPlanParams q) {
   uint32_t run_large = 0, run_tiles = 0, run_small = 0;
   for (uint32_t base = 0; base < q.nseg; base += BLOCK) {
     const uint32_t s = base + t;
-    uint64_t len = 0;
-    if (s < q.nseg) len = q.seg_hi[s] - q.seg_lo[s];
     const bool in = s < q.nseg;
+    SegBounds sb{0, 0};
+    if (in) sb = resolve_segment(q.seg_lo[s], q.seg_hi[s], q.extent);
+    const uint64_t lo = sb.lo;
+    uint64_t len = sb.len;
     const bool large = in && len > q.small_max;
+    const uint32_t want = large ? (uint32_t)((len + q.tile - 1) / q.tile) : 0u;
     sh_large[t] = large ? 1u : 0u;
-    sh_tiles[t] = large ? (uint32_t)((len + q.tile - 1) / q.tile) : 0u;
+    sh_tiles[t] = want;
     sh_small[t] = (in && !large) ? 1u : 0u;
     __syncthreads();
     const uint32_t tl = block_exclusive_scan<BLOCK>(sh_large, BLOCK, wsum);
     const uint32_t tt = block_exclusive_scan<BLOCK>(sh_tiles, BLOCK, wsum);
     const uint32_t ts = block_exclusive_scan<BLOCK>(sh_small, BLOCK, wsum);
+    // tiles before this array, and its own, cut at the bound (run_tiles is
+    // at most the bound)
+    const TileRange tr = cut_tiles((uint64_t)run_tiles + sh_tiles[t], want, q.tiles_bound);
     if (large) {
       q.large_ids[run_large + sh_large[t]] = s;
-      q.tile_base[run_large + sh_large[t]] = run_tiles + sh_tiles[t];
+      q.tile_base[run_large + sh_large[t]] = tr.first;
+      const uint64_t fits = (uint64_t)(tr.last - tr.first) * q.tile;
+      if (len > fits) len = fits;
     } else if (in) {
       q.small_ids[run_small + sh_small[t]] = s;
     }
+    if (in) {
+      q.rlo[s] = lo;
+      q.rhi[s] = lo + len;
+    }
     run_large += tl;
-    run_tiles += tt;
+    run_tiles = cut_tiles(run_tiles, tt, q.tiles_bound).last;
     run_small += ts;
     __syncthreads();
   }

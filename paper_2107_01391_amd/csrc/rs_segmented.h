@@ -44,9 +44,15 @@ rs_status run_segmented(const Plan &p, const SegLayout &L, const Digit *digits, 
   uint32_t *sums = (uint32_t *)(base + L.off_sums);
   rs_status st;
 
-  SegPlanParams q{seg_lo, seg_hi, L.nseg, L.small_max, L.tile, nlarge, large_ids, tile_base, nsmall, small_ids};
+  // the caller's bounds are read once, by rs_seg_plan; every later kernel
+  // reads the resolved (clamped) copy
+  uint64_t *rlo = (uint64_t *)(base + L.off_bounds), *rhi = rlo + L.nseg;
+  SegPlanParams q{seg_lo, seg_hi, L.nseg, L.small_max, L.tile, L.extent, (uint32_t)L.tiles_bound,
+                  nlarge, large_ids, tile_base, nsmall, small_ids, rlo, rhi};
   RS_TIMED("rs_seg_plan", stream, hipLaunchKernelGGL((rs_seg_plan<1024>), dim3(1), dim3(1024), 0, stream, q));
   if ((st = check_launch("rs_seg_plan")) != RS_OK) return st;
+  seg_lo = rlo;
+  seg_hi = rhi;
   if (L.any_large) {
     SegTilesParams tq{seg_lo, seg_hi, large_ids, tile_base, nlarge, L.tile, tiles, ntotal};
     RS_TIMED("rs_seg_tiles", stream,

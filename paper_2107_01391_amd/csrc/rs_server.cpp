@@ -424,7 +424,7 @@ rs_status rs_server_create(const rs_key_desc *desc, const rs_server_config *cfg,
 }
 
 rs_status rs_server_submit(rs_server *s, const void *keys, const uint32_t *vals, uint64_t n, uint64_t arrival_ns,
-                           uint64_t *ticket) {
+                           void *src_stream, uint64_t *ticket) {
   g_last_error.clear();
   if (!s || !ticket) return fail(RS_ERR_NULL_ARG, "server and ticket are required");
   if (n && (!keys || (s->cfg.with_values && !vals))) return fail(RS_ERR_NULL_ARG, "keys (and values) are required");
@@ -452,7 +452,14 @@ rs_status rs_server_submit(rs_server *s, const void *keys, const uint32_t *vals,
     return RS_OK;
   }
   const size_t kb = s->key_plan.key.key_bytes;
-  bool ok = hipMemcpyAsync(s->kin + off * kb, keys, n * kb, hipMemcpyDefault, s->upload) == hipSuccess;
+  // the upload stream does not synchronise with other streams: it first
+  // waits for what the producer has enqueued on src_stream (the writes of
+  // the sources), so the copies read finished data
+  hipEvent_t produced = s->take_event();
+  bool ok = produced && hipEventRecord(produced, (hipStream_t)src_stream) == hipSuccess &&
+            hipStreamWaitEvent(s->upload, produced, 0) == hipSuccess;
+  if (produced) s->event_pool.push_back(produced);  // the wait is enqueued: the event may be recorded again
+  if (ok) ok = hipMemcpyAsync(s->kin + off * kb, keys, n * kb, hipMemcpyDefault, s->upload) == hipSuccess;
   if (ok && s->cfg.with_values)
     ok = hipMemcpyAsync(s->vin + off, vals, n * 4, hipMemcpyDefault, s->upload) == hipSuccess;
   if (!ok) {

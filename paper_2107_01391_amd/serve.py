@@ -1,7 +1,14 @@
 """Served request loop (rs_server, C++) from Python, and a trace driver.
 
-A Server owns nothing but the C handle: its device arenas and scratch are
-torch tensors allocated here and kept alive with it.  run_trace() replays an
+A Server owns the C handle; its device arenas and scratch are torch tensors
+allocated here and kept alive with it.  The server copies a request's keys
+and values into its arena on its own upload stream, after submit() has
+returned, so submit() keeps a reference to the tensors it was given until
+the request is released (or the server closed): a caller may pass
+temporaries, and torch's allocator cannot hand their memory to another
+tensor while the copy may still read it.  The copy also waits for the work
+already enqueued on torch's current stream, where the sources were written.
+run_trace() replays an
 arrival trace (seeded Poisson arrivals, log-uniform sizes) against a server,
 submitting each request at its arrival time, retrying while admission says
 busy, and releasing each result once done; it returns the server's latency
@@ -50,6 +57,7 @@ class Server:
                                       self.keys_out.data_ptr(), vi, vo, self.work.data_ptr(), need.value,
                                       ctypes.byref(h)))
         self._h = h.value
+        self._held = {}  # ticket -> the submitted source tensors, until release
 
     @staticmethod
     def clock() -> int:
@@ -58,15 +66,23 @@ class Server:
         return t.value
 
     def submit(self, keys, vals=None, n: int | None = None, arrival_ns: int = 0) -> int | None:
-        """Ticket, or None when admission refuses the request now (busy)."""
+        """Ticket, or None when admission refuses the request now (busy).
+        keys / vals (tensors) are held until the ticket is released."""
+        import torch
         lib = B.load_library()
         n = keys.numel() if n is None else n
         t = ctypes.c_uint64(0)
-        st = lib.rs_server_submit(self._h, B._ptr(keys), B._ptr(vals), n, arrival_ns, ctypes.byref(t))
+        src_stream = torch.cuda.current_stream().cuda_stream if getattr(keys, "is_cuda", False) else None
+        st = lib.rs_server_submit(self._h, B._ptr(keys), B._ptr(vals), n, arrival_ns, src_stream, ctypes.byref(t))
         if st == B.RS_ERR_BUSY:
             return None
         B._check(st)
+        self._held[t.value] = (keys, vals)
         return t.value
+
+    def held(self) -> int:
+        """Requests whose source tensors are still referenced."""
+        return len(self._held)
 
     def done(self, ticket: int) -> bool:
         d = ctypes.c_int(0)
@@ -94,6 +110,7 @@ class Server:
 
     def release(self, ticket: int) -> None:
         B._check(B.load_library().rs_server_release(self._h, ticket))
+        self._held.pop(ticket, None)
 
     def stats(self) -> dict:
         s = B.ServerStats()
@@ -107,6 +124,7 @@ class Server:
         if self._h:
             B._check(B.load_library().rs_server_destroy(self._h))
             self._h = None
+        self._held.clear()  # destroy has waited for every upload
 
     def __del__(self):
         try:

@@ -191,3 +191,40 @@ def test_batched_validate_rejects_bad_offsets(offs):
     torch.cuda.synchronize()
     got = api.to_host(ko, np.uint32, (10,))
     assert got.tolist() == sorted(keys[:3].tolist()) + sorted(keys[3:].tolist())
+
+
+@pytest.mark.parametrize("offs", [[0, 20_000, 5_000, 60_000, 1 << 40, 3, 50_000],
+                                  [0, 50_000, 0, 50_000, 0, 50_000, 0],
+                                  [7, 3, (1 << 64) - 1, 0, 49_999, 50_000, 50_000]])
+def test_batched_bad_offsets_stay_in_bounds(offs, tile_block):
+    """Without validation, offsets that decrease, overlap or point past the
+    end give an unspecified order but no access outside the buffers: the
+    arrays' bounds are clamped on the device before any kernel reads keys
+    (overlapping arrays also have their tiles cut at the scratch's bound).
+    The outputs sit between guard bands that must come back untouched, and
+    the same scratch then sorts valid offsets correctly."""
+    import torch
+    _say(f"batched bad offsets {offs} tile_block={tile_block}")
+    total, nseg, guard = 50_000, len(offs) - 1, 1 << 16
+    d = B.key_desc("u32", base=256, ndims=4)
+    keys, vals, good = workloads.batched_u32(count=nseg, lo=1000, hi=20_000)
+    keys = np.resize(keys, total).astype(np.uint32)
+    vals = np.arange(total, dtype=np.uint32)
+    kd, vd = api.to_device(keys), api.to_device(vals)
+    kbuf = torch.full((total + 2 * guard,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+    vbuf = torch.full((total + 2 * guard,), 0x3C3C3C3C, dtype=torch.int32, device="cuda")
+    ko, vo = kbuf[guard:guard + total], vbuf[guard:guard + total]
+    tmp = api.empty_device(B.rs_batched_temp_bytes(d, total, nseg, True))
+    od = api.to_device(np.array(offs, dtype=np.uint64))
+    B.rs_sort_batched(d, kd, ko, vd, vo, od, nseg, total, tmp, tmp.numel())
+    torch.cuda.synchronize()
+    for buf, fill in ((kbuf, 0x5A5A5A5A), (vbuf, 0x3C3C3C3C)):
+        assert bool((buf[:guard] == fill).all()) and bool((buf[guard + total:] == fill).all()), "guard band written"
+    # the same scratch, valid offsets
+    goff = np.linspace(0, total, nseg + 1).astype(np.uint64)
+    od = api.to_device(goff)
+    B.rs_sort_batched(d, kd, ko, vd, vo, od, nseg, total, tmp, tmp.numel())
+    torch.cuda.synchronize()
+    gk, gv = ko.cpu().numpy().view(np.uint32), vo.cpu().numpy().view(np.uint32)
+    ok, ov = oracle_batched(keys, vals, goff, "u32", 256, 4)
+    _cmp(gk, gv, ok, ov, goff)

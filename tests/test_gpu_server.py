@@ -152,7 +152,9 @@ def test_signed_descending_server(mode):
     vals = [rng.permutation(n).astype(np.uint32) for n in sizes]
     srv = Server(desc, capacity=400_000, max_slots=16, streams=2, mode=mode)
     try:
-        tickets = [srv.submit(api.to_device(k), api.to_device(v), k.shape[0]) for k, v in zip(keys, vals)]
+        dev = [(api.to_device(k), api.to_device(v)) for k, v in zip(keys, vals)]  # alive until the end
+        tickets = [srv.submit(dk, dv, k.shape[0]) for (dk, dv), k in zip(dev, keys)]
+        assert srv.held() == len(tickets)
         for t in tickets:
             srv.wait(t)
         for t, k, v in zip(tickets, keys, vals):
@@ -161,6 +163,42 @@ def test_signed_descending_server(mode):
             assert np.array_equal(rk.cpu().numpy().view(np.int32), ok)
             assert np.array_equal(rv.cpu().numpy().view(np.uint32), ov)
             srv.release(t)
+        assert srv.held() == 0
+    finally:
+        srv.close()
+
+
+@pytest.mark.parametrize("mode", [B.RS_SERVE_BATCHED, B.RS_SERVE_PER_REQUEST])
+def test_submit_temporaries(mode):
+    """Requests submitted as temporaries that the caller drops at once,
+    while new tensors are allocated and written on torch's stream: the
+    server holds each request's sources until it is released, so every
+    result is still the sort of its own request."""
+    _say(f"server temporaries mode={mode}")
+    import torch
+    desc = B.key_desc("u32", base=256, ndims=4)
+    rng = np.random.default_rng(78)
+    sizes = [4097, 1, 30_000, 4096, 250_000, 70_001, 5, 100_000]
+    keys = [rng.integers(0, 2**32, n, dtype=np.uint32) for n in sizes]
+    vals = [rng.permutation(n).astype(np.uint32) for n in sizes]
+    srv = Server(desc, capacity=600_000, max_slots=16, streams=2, mode=mode)
+    try:
+        tickets = []
+        for k, v in zip(keys, vals):
+            tickets.append(srv.submit(api.to_device(k), api.to_device(v), k.shape[0]))
+            # blocks a freed source would be handed to: overwrite them now
+            junk = torch.full((300_000,), -1, dtype=torch.int32, device="cuda")
+            del junk
+        assert srv.held() == len(tickets)
+        for t in tickets:
+            srv.wait(t)
+        for t, k, v in zip(tickets, keys, vals):
+            rk, rv = srv.result(t)
+            ok, ov = oracle_sort(k, v, "u32", 256, 4)
+            assert np.array_equal(rk.cpu().numpy().view(np.uint32), ok)
+            assert np.array_equal(rv.cpu().numpy().view(np.uint32), ov)
+            srv.release(t)
+        assert srv.held() == 0
     finally:
         srv.close()
 

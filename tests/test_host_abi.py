@@ -124,6 +124,21 @@ def test_codec_host_build(tmp_path):
     assert "codec ok" in r.stdout
 
 
+def test_seg_bounds_host_build(tmp_path):
+    """The batched form's resolution of the caller's offsets (the arithmetic
+    of rs_seg_plan), built for the host from the header the kernel uses:
+    valid offsets pass unchanged; any offsets stay inside the buffers and the
+    scratch's tile bound."""
+    src = os.path.join(ROOT, "tests", "seg_bounds_check.cpp")
+    exe = str(tmp_path / "seg_bounds_check")
+    subprocess.run(["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-x", "hip", "--cuda-host-only", "-I",
+                    os.path.join(ROOT, "paper_2107_01391_amd", "csrc"), "-I", os.path.join(ROOT, "include"), src,
+                    "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "seg bounds ok" in r.stdout
+
+
 # ------------------------------------------------------------ tuning table
 
 def test_tuning_defaults_set_get_clear_and_file(tmp_path):
