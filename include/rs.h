@@ -134,6 +134,27 @@ rs_status rs_sort_keys(const rs_key_desc *desc, const void *keys_in, void *keys_
 rs_status rs_sort_pairs(const rs_key_desc *desc, const void *keys_in, void *keys_out, const uint32_t *vals_in,
                         uint32_t *vals_out, uint64_t n, void *tmp, size_t tmp_bytes, void *stream);
 
+/* Size of the library's static device scratch (64 MiB per device). */
+#define RS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* rs_sort_pairs without a tmp argument, for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, results and rules as
+ * rs_sort_pairs; the scratch is a static array inside the library, one
+ * RS_NOALLOC_SCRATCH_BYTES copy per device, held from the first call on that
+ * device until the process ends.  The call allocates nothing (no hipMalloc,
+ * no hipFree).
+ *   Limit: a sort whose rs_temp_bytes(desc, n, 1) exceeds
+ *   RS_NOALLOC_SCRATCH_BYTES returns RS_ERR_UNSUPPORTED and launches nothing
+ *   (with the default tuning: u32 pairs up to 8,259,392 keys, u64 pairs up
+ *   to 5,534,688, 16-byte strings up to 3,132,288).
+ *   Every call on a device shares that device's array: calls that overlap in
+ *   time on one device (other streams or threads, no ordering between them)
+ *   race and give unspecified results.  Calls ordered on one stream are safe;
+ *   nothing a call leaves in the array affects the next one. */
+rs_status rs_sort_pairs_noalloc(const rs_key_desc *desc, const void *keys_in, void *keys_out,
+                                const uint32_t *vals_in, uint32_t *vals_out, uint64_t n, void *stream);
+
 /* Scratch bytes for rs_sort_batched over nseg arrays holding `total` keys. */
 rs_status rs_batched_temp_bytes(const rs_key_desc *desc, uint64_t total, uint32_t nseg, int with_values,
                                 size_t *bytes);

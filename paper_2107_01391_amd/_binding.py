@@ -20,11 +20,13 @@ RS_KEY_U32, RS_KEY_U64, RS_KEY_FIXED_I64, RS_KEY_STR, RS_KEY_I32, RS_KEY_I64 = 0
 RS_FLAG_VALIDATE = 1
 RS_FLAG_DESCENDING = 2
 RS_MAX_ELEMENTS = (1 << 30) - 1
+RS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 KINDS = {"u32": RS_KEY_U32, "u64": RS_KEY_U64, "fixed_i64": RS_KEY_FIXED_I64, "str": RS_KEY_STR,
          "i32": RS_KEY_I32, "i64": RS_KEY_I64}
 
-EXPORTED = ["rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_batched_temp_bytes", "rs_sort_batched",
+EXPORTED = ["rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_sort_pairs_noalloc", "rs_batched_temp_bytes",
+            "rs_sort_batched",
             "rs_status_string", "rs_last_error", "rs_prof_enable", "rs_prof_query",
             "rs_tuning_get", "rs_tuning_set", "rs_tuning_clear", "rs_tune_temp_bytes", "rs_tune_sort",
             "rs_tune_batched", "rs_tuning_save", "rs_tuning_load",
@@ -98,9 +100,11 @@ def load_library(path: str | None = None):
     lib.rs_temp_bytes.argtypes = [dp, u64, ctypes.c_int, ctypes.POINTER(sz)]
     lib.rs_sort_keys.argtypes = [dp, vp, vp, u64, vp, sz, vp]
     lib.rs_sort_pairs.argtypes = [dp, vp, vp, vp, vp, u64, vp, sz, vp]
+    lib.rs_sort_pairs_noalloc.argtypes = [dp, vp, vp, vp, vp, u64, vp]
     lib.rs_batched_temp_bytes.argtypes = [dp, u64, u32, ctypes.c_int, ctypes.POINTER(sz)]
     lib.rs_sort_batched.argtypes = [dp, vp, vp, vp, vp, vp, u32, u64, vp, sz, vp]
-    for f in ("rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_batched_temp_bytes", "rs_sort_batched"):
+    for f in ("rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_sort_pairs_noalloc", "rs_batched_temp_bytes",
+              "rs_sort_batched"):
         getattr(lib, f).restype = ctypes.c_int
     lib.rs_status_string.argtypes = [ctypes.c_int]
     lib.rs_status_string.restype = ctypes.c_char_p
@@ -199,6 +203,12 @@ def rs_sort_pairs(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, n: int, t
                   stream=None) -> None:
     _check(load_library().rs_sort_pairs(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
                                         _ptr(vals_out), n, _ptr(tmp), tmp_bytes, _stream(stream)))
+
+
+def rs_sort_pairs_noalloc(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, n: int, stream=None) -> None:
+    """rs_sort_pairs with the library's static device scratch (no tmp)."""
+    _check(load_library().rs_sort_pairs_noalloc(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
+                                                _ptr(vals_out), n, _stream(stream)))
 
 
 def rs_batched_temp_bytes(desc: KeyDesc, total: int, nseg: int, with_values: bool) -> int:

@@ -19,6 +19,10 @@ rs_status check_alignment(const KeyInfo &k, const void *ki, const void *ko, cons
                           const void *tmp);
 rs_status launch_fill(void *p, size_t bytes, uint32_t value, hipStream_t stream);
 rs_status validate_keys(const Plan &pl, const void *keys, uint64_t n, void *tmp, hipStream_t s);
+// rs_sort_keys (pairs = false) / rs_sort_pairs (pairs = true) on a given
+// scratch buffer: argument checks, plan, optional validation, launches.
+rs_status sort_common(const rs_key_desc *desc, const void *keys_in, void *keys_out, const uint32_t *vals_in,
+                      uint32_t *vals_out, uint64_t n, void *tmp, size_t tmp_bytes, void *stream, bool pairs);
 rs_status run_plan(const Plan &pl, const void *ki, void *ko, const uint32_t *vi, uint32_t *vo, void *tmp,
                    hipStream_t s);
 

@@ -425,6 +425,29 @@ rs_status run_plan(const Plan &pl, const void *ki, void *ko, const uint32_t *vi,
   return fail(RS_ERR_BAD_DESC, "unknown digit mode");
 }
 
+rs_status sort_common(const rs_key_desc *desc, const void *keys_in, void *keys_out, const uint32_t *vals_in,
+                      uint32_t *vals_out, uint64_t n, void *tmp, size_t tmp_bytes, void *stream, bool pairs) {
+  g_last_error.clear();
+  if (!desc) return fail(RS_ERR_NULL_ARG, "desc is NULL");
+  if (n == 0) return RS_OK;
+  if (!keys_in || !keys_out || !tmp) return fail(RS_ERR_NULL_ARG, "keys_in, keys_out and tmp are required");
+  if (pairs && (!vals_in || !vals_out)) return fail(RS_ERR_NULL_ARG, "vals_in and vals_out are required");
+  Plan pl;
+  std::string why;
+  rs_status st = make_plan(desc, n, pairs, current_tuning(desc, n, pairs), &pl, &why);
+  if (st != RS_OK) return fail(st, why);
+  if (tmp_bytes < pl.total)
+    return fail(RS_ERR_TMP_TOO_SMALL, "tmp_bytes " + std::to_string(tmp_bytes) + " < " + std::to_string(pl.total));
+  if ((st = check_alignment(pl.key, keys_in, keys_out, vals_in, vals_out, tmp)) != RS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (desc->flags & RS_FLAG_VALIDATE) {
+    st = validate_keys(pl, keys_in, n, tmp, s);
+    if (st != RS_OK) return st;
+  }
+  return run_plan(pl, keys_in, keys_out, vals_in, vals_out, tmp, s);
+}
+
+
 }  // namespace rs
 
 using namespace rs;
@@ -457,29 +480,6 @@ rs_status rs_temp_bytes(const rs_key_desc *desc, uint64_t n, int with_values, si
   if (st != RS_OK) return fail(st, why);
   *bytes = pl.total;
   return RS_OK;
-}
-
-static rs_status sort_common(const rs_key_desc *desc, const void *keys_in, void *keys_out, const uint32_t *vals_in,
-                             uint32_t *vals_out, uint64_t n, void *tmp, size_t tmp_bytes, void *stream,
-                             bool pairs) {
-  g_last_error.clear();
-  if (!desc) return fail(RS_ERR_NULL_ARG, "desc is NULL");
-  if (n == 0) return RS_OK;
-  if (!keys_in || !keys_out || !tmp) return fail(RS_ERR_NULL_ARG, "keys_in, keys_out and tmp are required");
-  if (pairs && (!vals_in || !vals_out)) return fail(RS_ERR_NULL_ARG, "vals_in and vals_out are required");
-  Plan pl;
-  std::string why;
-  rs_status st = make_plan(desc, n, pairs, current_tuning(desc, n, pairs), &pl, &why);
-  if (st != RS_OK) return fail(st, why);
-  if (tmp_bytes < pl.total)
-    return fail(RS_ERR_TMP_TOO_SMALL, "tmp_bytes " + std::to_string(tmp_bytes) + " < " + std::to_string(pl.total));
-  if ((st = check_alignment(pl.key, keys_in, keys_out, vals_in, vals_out, tmp)) != RS_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  if (desc->flags & RS_FLAG_VALIDATE) {
-    st = validate_keys(pl, keys_in, n, tmp, s);
-    if (st != RS_OK) return st;
-  }
-  return run_plan(pl, keys_in, keys_out, vals_in, vals_out, tmp, s);
 }
 
 rs_status rs_sort_keys(const rs_key_desc *desc, const void *keys_in, void *keys_out, uint64_t n, void *tmp,

@@ -286,3 +286,21 @@ def test_short_arrays_plan_one_workgroup():
         assert B.rs_temp_bytes(dd, 4096, True) == 256
     s = B.key_desc("str", base=27, ndims=16)
     assert B.rs_temp_bytes(s, 100, True) > 100 * 16
+
+
+def test_noalloc_sort_checks_before_any_device_call():
+    """rs_sort_pairs_noalloc: n == 0 is a no-op, a NULL description is
+    refused, and a sort whose scratch exceeds the static array is refused
+    with RS_ERR_UNSUPPORTED before the array is looked up or anything runs."""
+    d = B.key_desc("u32", base=256, ndims=4)
+    lib = B.load_library()
+    assert lib.rs_sort_pairs_noalloc(ctypes.byref(d), None, None, None, None, 0, None) == 0
+    fake = ctypes.c_void_p(256)
+    assert lib.rs_sort_pairs_noalloc(None, fake, fake, fake, fake, 10, None) == 1
+    n_max = 1
+    while B.rs_temp_bytes(d, n_max * 2, True) <= B.RS_NOALLOC_SCRATCH_BYTES:
+        n_max *= 2
+    too_big = 1 << 24
+    assert B.rs_temp_bytes(d, too_big, True) > B.RS_NOALLOC_SCRATCH_BYTES
+    assert lib.rs_sort_pairs_noalloc(ctypes.byref(d), fake, fake, fake, fake, too_big, None) == 5
+    assert "static scratch" in B.rs_last_error()
