@@ -31,8 +31,24 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Gkeys/s + % HBM peak, 256M u32 KV sort; batched vs per-array at p99 latency"
 HBM_PEAK_GBS = 8000.0
 FULL_N = 1 << 28
-PMC_FILE = os.path.join(ROOT, "profiles", "rank_scatter_u32_pairs_268M_pmc.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2107_01391_amd", "csrc", f) for f in ("rs_kernels.h", "rs_device.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2107_01391_amd", "csrc", f)
+                  for f in ("rs_kernels.h", "rs_device.h", "rs_passes.h", "rs_sort.hip", "rs_seg_kernels.h")]
+# The other full-size workloads: keys-only decimals over the literal 10^6-cell
+# space, fixed-point decimals, and 16-byte strings; algorithmic bytes per key
+# are the method's minimum (hash read of the key; scatter read and write of
+# key and value; keys only: the key read and written once more).
+WORKLOADS = {
+    "uniform_decimal_u32": {"kind": "u32", "base": 10, "ndims": 6, "frac": 0, "pairs": False, "alg_bytes": 12,
+                            "what": "1,000,000 uint32 keys uniform in [0, 10^6), keys only, base 10, 6 dimensions "
+                                    "(literal 10^6-cell space)"},
+    "fixed_point_decimals": {"kind": "fixed_i64", "base": 10, "ndims": 9, "frac": 3, "pairs": True,
+                             "alg_bytes": 32,
+                             "what": "100,000,000 int64 fixed-point decimals (x1000, lognormal, 30% integral, "
+                                     "10% repeats), uint32 index payload, base 10, 9 dimensions"},
+    "strings16": {"kind": "str", "base": 27, "ndims": 16, "frac": 0, "pairs": True, "alg_bytes": 56,
+                  "what": "16,777,216 zero-padded 16-byte lowercase strings, uint32 index payload, base 27, "
+                          "16 dimensions"},
+}
 
 
 def kernel_source_sha() -> str:
@@ -43,11 +59,15 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def pmc_summary(n: int):
-    """The committed PMC summary, or None when it is missing, for another
-    size, or the kernels changed since the counters were taken."""
+def pmc_file(name: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{name}_pmc.json")
+
+
+def pmc_summary(n: int, name: str = "uniform_u32_pairs"):
+    """The committed PMC summary of a workload, or None when it is missing,
+    for another size, or the kernels changed since the counters were taken."""
     try:
-        with open(PMC_FILE) as f:
+        with open(pmc_file(name)) as f:
             pmc = json.load(f)
     except (OSError, ValueError):
         return None
@@ -56,33 +76,121 @@ def pmc_summary(n: int):
     return pmc
 
 
+def _kernel_bytes(pmc: dict, prefix: str):
+    """Scaled HBM bytes per dispatch of the kernels whose name starts with
+    `prefix`, summed over those kernels (each a per-dispatch average)."""
+    rows = [v for k, v in pmc["kernels"].items() if k.startswith(prefix)]
+    return sum(r["bytes_per_dispatch"] for r in rows) if rows else None
+
+
 def measured_traffic(n: int):
     """HBM bytes per rs_rank_scatter launch (PMC), or None."""
     pmc = pmc_summary(n)
-    return pmc.get("hbm_bytes_per_launch") if pmc else None
+    return _kernel_bytes(pmc, "rs::rs_rank_scatter") if pmc else None
 
 
 def measured_pass_bytes(n: int):
     """HBM bytes of one whole pass (count, scan, scatter; PMC), or None."""
     pmc = pmc_summary(n)
-    try:
-        return (pmc["hbm_bytes_per_launch"] + pmc["rs_tile_histogram"]["bytes_scaled"]
-                + pmc["rs_cell_scan"]["bytes_scaled"])
-    except (TypeError, KeyError):
+    if not pmc or not pmc.get("passes"):
         return None
+    return pmc["bytes_per_sort"] / pmc["passes"]
+
+
+def summarize_pmc(name: str, fetch_csv: str, write_csv: str, sorts: int, passes: int | None, n: int,
+                  command: list[str]) -> dict:
+    """Per-kernel FETCH_SIZE / WRITE_SIZE (KiB per dispatch, from two
+    rocprofv3 --pmc runs of `bench.py --workload NAME --copy-calibration`),
+    scaled by what the same counters read for the calibration copy kernel
+    (torch's bitwise_not over 1 GiB: 1 GiB read, 1 GiB written)."""
+    import csv
+    from collections import defaultdict
+
+    def short(name):
+        # "void rs::k<T, ...>(args)" -> "rs::k<T, ...>"
+        name = name[5:] if name.startswith("void ") else name
+        depth = 0
+        for i, c in enumerate(name):
+            depth += (c == "<") - (c == ">")
+            if c == "(" and depth == 0:
+                return name[:i]
+        return name
+
+    def read(path, counter):
+        per = defaultdict(list)
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                per[short(row["Kernel_Name"])].append(float(row["Counter_Value"]))
+        return per
+
+    fetch, write = read(fetch_csv, "FETCH_SIZE"), read(write_csv, "WRITE_SIZE")
+    cal_f = [v for k, vs in fetch.items() if "bitwise_not" in k for v in vs]
+    cal_w = [v for k, vs in write.items() if "bitwise_not" in k for v in vs]
+    gib_kib = float(1 << 20)
+    fs = gib_kib / (sum(cal_f) / len(cal_f))
+    ws = gib_kib / (sum(cal_w) / len(cal_w))
+    kernels = {}
+    total = 0.0
+    for k in sorted(set(fetch) | set(write)):
+        if not k.startswith("rs::"):
+            continue
+        f, w = fetch.get(k, []), write.get(k, [])
+        fa = sum(f) / len(f) if f else 0.0
+        wa = sum(w) / len(w) if w else 0.0
+        b = int(round((fa * fs + wa * ws) * 1024))
+        kernels[k] = {"dispatches": max(len(f), len(w)), "FETCH_SIZE_KiB_avg": round(fa, 1),
+                      "WRITE_SIZE_KiB_avg": round(wa, 1), "bytes_per_dispatch": b}
+        total += b * max(len(f), len(w))
+    return {"workload": name, "n": n, "kernel_source_sha": kernel_source_sha(), "commands": command,
+            "calibration": {"kernel": "torch bitwise_not over 2^28 int32 (1 GiB read + 1 GiB write)",
+                            "fetch_scale": round(fs, 5), "write_scale": round(ws, 5)},
+            "sorts": sorts, "passes": passes, "bytes_per_sort": int(round(total / sorts)), "kernels": kernels}
+
+
+CPU_FULL_FILE = os.path.join(ROOT, "profiles", "cpu_oracle_u32_pairs_268M.json")
 
 
 def cpu_baseline(w, sample: int) -> dict:
+    """The oracle, single-threaded, on the first `sample` pairs.  Its rate
+    falls with n (the 2 GiB arrays of the full size miss the host caches
+    that a sample's arrays hit), so the full-size time measured once on the
+    GPU host (--cpu-full, profiles/cpu_oracle_u32_pairs_268M.json) is
+    reported beside it when present."""
     import oracle
     oracle.build(force=False)
     keys, vals = w.keys[:sample], w.vals[:sample]
     t0 = time.perf_counter()
     oracle.sort(keys, vals, kind="u32", base=256, ndims=4, groups=oracle.DEFAULT_GROUPS["uniform_u32_pairs"])
     dt = time.perf_counter() - t0
-    return {"value": round(sample / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample} pairs of the same seeded input; single-threaded C oracle, gcc -O2, "
-                      f"dimension groups [1, 3] (256 buckets, then one 2^24-cell space per bucket); "
-                      f"{dt:.1f} s", "seconds": round(dt, 2)}
+    out = {"value": round(sample / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "host_cores": os.cpu_count(),
+           "kind": "oracle",
+           "sample": f"first {sample} pairs of the same seeded input; single-threaded C oracle, gcc -O2, "
+                     f"dimension groups [1, 3] (256 buckets, then one 2^24-cell space per bucket); "
+                     f"{dt:.1f} s; the rate at the full 2^28 is lower (see full_size)", "seconds": round(dt, 2)}
+    try:
+        with open(CPU_FULL_FILE) as f:
+            full = json.load(f)
+        out["full_size"] = {k: full[k] for k in ("n", "seconds", "gkeys_per_s", "host_cores", "host") if k in full}
+    except (OSError, ValueError):
+        out["full_size"] = None
+    return out
+
+
+def cpu_full(w) -> dict:
+    """The oracle once on the whole input (minutes), for the record."""
+    import platform
+
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.sort(w.keys, w.vals, kind="u32", base=256, ndims=4, groups=oracle.DEFAULT_GROUPS["uniform_u32_pairs"])
+    dt = time.perf_counter() - t0
+    return {"what": "CPU oracle (single-threaded C, gcc -O2, groups [1, 3]) on the full uniform_u32_pairs input",
+            "command": "python bench.py --cpu-full", "n": w.n, "seconds": round(dt, 1),
+            "gkeys_per_s": round(w.n / dt / 1e9, 6), "cores": 1, "host_cores": os.cpu_count(),
+            "host": platform.processor() or platform.machine()}
 
 
 def check_sorted(torch, keys_in, keys_out, vals_out, n):
@@ -113,13 +221,146 @@ def oracle_digest_match(keys_out, vals_out, n: int):
     return hk == rec["keys_sha256"] and hv == rec["vals_sha256"]
 
 
+def calibration_copy(torch) -> None:
+    """A plain streaming kernel of known size for the PMC byte counters:
+    reads 1 GiB and writes 1 GiB (torch's elementwise bitwise_not)."""
+    a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(2):
+        torch.bitwise_not(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+
+
+PROF_KERNELS = ("rs_tile_histogram", "rs_cell_scan", "rs_rank_scatter", "rs_digit_hash_histogram", "rs_fill",
+                "rs_cell_count", "rs_cell_emit", "rs_narrow", "rs_widen", "rs_small_sort", "rs_copy")
+
+
+def run_workload(torch, B, api, workloads, name: str, steps: int, warmup: int) -> dict:
+    """One of WORKLOADS at full size through rs_sort_pairs / rs_sort_keys
+    with the default tuning: median whole-sort time over `steps` event-timed
+    sorts, per-kernel time (HIP events on the launch stream), the output's
+    SHA-256 against the oracle's digest, and the whole sort's share of the
+    HBM peak from the algorithmic bytes and from the committed counters."""
+    spec = WORKLOADS[name]
+    print(f"[bench] {name}: generating", file=sys.stderr, flush=True)
+    w = getattr(workloads, name)()
+    n = w.n
+    d = B.key_desc(spec["kind"], base=spec["base"], ndims=spec["ndims"], frac_digits=spec["frac"])
+    keys = api.to_device(w.keys)
+    vals = api.to_device(w.vals) if spec["pairs"] else None
+    del w
+    ko = torch.empty_like(keys)
+    vo = torch.empty_like(vals) if vals is not None else None
+    tmp = api.empty_device(B.rs_temp_bytes(d, n, spec["pairs"]))
+    stream = torch.cuda.current_stream()
+
+    def once():
+        if spec["pairs"]:
+            B.rs_sort_pairs(d, keys, ko, vals, vo, n, tmp, tmp.numel(), stream)
+        else:
+            B.rs_sort_keys(d, keys, ko, n, tmp, tmp.numel(), stream)
+
+    for _ in range(warmup):
+        once()
+    torch.cuda.synchronize()
+    B.rs_prof_enable(True)
+    evs = []
+    for _ in range(steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        once()
+        b.record(stream)
+        evs.append((a, b))
+    torch.cuda.synchronize()
+    kern = {}
+    for k in PROF_KERNELS:
+        c, ms_k = B.rs_prof_query(k)
+        if c:
+            kern[k] = {"launches_per_sort": c // steps, "ms_per_sort": round(ms_k / steps, 4)}
+    B.rs_prof_enable(False)
+    times = sorted(a.elapsed_time(b) for a, b in evs)
+    ms = times[len(times) // 2]
+    digest = None
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", "digests.json")) as f:
+            rec = json.load(f)["workloads"][name]
+        if rec.get("n") == n:
+            kb = keys.numel()
+            digest = hashlib.sha256(ko[:kb].cpu().numpy().data).hexdigest() == rec["keys_sha256"]
+            if vo is not None:
+                digest = digest and hashlib.sha256(vo[: 4 * n].cpu().numpy().data).hexdigest() == rec["vals_sha256"]
+    except (OSError, ValueError, KeyError):
+        pass
+    alg = spec["alg_bytes"] * n
+    line = {"workload": name, "what": spec["what"], "n": n, "ms": round(ms, 4), "ms_min": round(times[0], 4),
+            "gkeys_per_s": round(n / (ms / 1e3) / 1e9, 3), "algorithmic_bytes_per_key": spec["alg_bytes"],
+            "algorithmic_frac_of_peak": round(alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "kernel_ms_per_sort": kern, "oracle_digest_match": digest}
+    pmc = pmc_summary(n, name)
+    line["measured_bytes_per_sort"] = pmc["bytes_per_sort"] if pmc else None
+    line["measured_frac_of_peak"] = (round(pmc["bytes_per_sort"] / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                                     if pmc else None)
+    del keys, vals, ko, vo, tmp
+    torch.cuda.empty_cache()
+    return line
+
+
+def graph_tuned_batched(torch, B, desc, keys, keys_out, vals, vals_out, off_dev, count: int, total: int,
+                        offsets) -> dict:
+    """The batched form as the workload states it: the autotuner picks the
+    pass width and tile shape on these arrays (rs_tune_batched), the
+    sequence is captured once as a HIP graph (rs_graph_sort_batched) and
+    replayed; replays are event-timed and their output spot-checked."""
+    st = torch.cuda.current_stream()
+    tt = torch.empty(B.rs_tune_temp_bytes(desc, total, count, True), dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    best, best_ms = B.rs_tune_batched(desc, keys, keys_out, vals, vals_out, off_dev, count, total, tt, tt.numel(),
+                                      st, reps=2)
+    tune_s = time.perf_counter() - t0
+    del tt
+    torch.cuda.empty_cache()
+    tmp = torch.empty(B.rs_batched_temp_bytes(desc, total, count, True), dtype=torch.uint8, device="cuda")
+    g = B.rs_graph_sort_batched(desc, keys, keys_out, vals, vals_out, off_dev, count, total, tmp, tmp.numel())
+    g.launch(st)
+    torch.cuda.synchronize()
+    reps = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        g.launch(st)
+        b.record(st)
+        b.synchronize()
+        reps.append(a.elapsed_time(b))
+    good = True
+    for i in (0, count // 3, count - 1):
+        lo, hi = int(offsets[i]), int(offsets[i + 1])
+        k = keys_out[lo:hi].to(torch.int64) & 0xFFFFFFFF
+        v = vals_out[lo:hi].to(torch.int64)
+        src = keys[lo:hi].to(torch.int64) & 0xFFFFFFFF
+        good = good and bool((k[1:] >= k[:-1]).all()) and bool((src[v] == k).all())
+        good = good and bool(((k[1:] != k[:-1]) | (v[1:] > v[:-1])).all())
+    g.close()
+    del tmp
+    torch.cuda.empty_cache()
+    ms = min(reps)
+    return {"makespan_ms": round(ms, 3), "p50_ms": round(ms, 3), "p99_ms": round(ms, 3),
+            "gkeys_per_s": round(total / (ms / 1e3) / 1e9, 3), "replays_ms": [round(r, 3) for r in reps],
+            "tuned": best.as_dict(), "tuner_best_ms": round(best_ms, 3), "tuning_seconds": round(tune_s, 2),
+            "spot_check": good}
+
+
 def batched_vs_per_array(torch, B, workloads, count: int) -> dict:
     """`count` arrays with log-uniform sizes in [2^10, 2^22] (the seeded size
     law), uniform u32 keys and local-index payloads drawn on the device.
     Per-array: one rs_sort_pairs call per array, on 1 and on 4 streams (the
     better is kept); an array's latency runs from the common start to the
     event after its own sort.  Batched: one rs_sort_batched sequence, in
-    which every array completes at the makespan."""
+    which every array completes at the makespan, eagerly with the default
+    tuning, and as the workload states it (graph_tuned): tuned, captured
+    once in a HIP graph, replayed."""
     from paper_2107_01391_amd import api
     sizes = workloads.batched_sizes(count)
     offsets = np.zeros(count + 1, dtype=np.uint64)
@@ -173,6 +414,10 @@ def batched_vs_per_array(torch, B, workloads, count: int) -> dict:
         res.setdefault("spot_check", True)
         res["spot_check"] = res["spot_check"] and good
     del tmp
+    torch.cuda.empty_cache()
+    res["graph_tuned"] = graph_tuned_batched(torch, B, desc, keys, keys_out, vals, vals_out, off_dev, count, total,
+                                             offsets)
+    B.rs_tuning_clear()
 
     per = []
     for nstreams in (1, 4):
@@ -206,6 +451,7 @@ def batched_vs_per_array(torch, B, workloads, count: int) -> dict:
     for k in ("batched", "per_array"):
         res[k]["gkeys_per_s"] = round(total / (res[k]["makespan_ms"] / 1e3) / 1e9, 3)
     res["batched_speedup"] = round(res["per_array"]["makespan_ms"] / res["batched"]["makespan_ms"], 3)
+    res["graph_tuned_speedup"] = round(res["per_array"]["makespan_ms"] / res["graph_tuned"]["makespan_ms"], 3)
     return res
 
 
@@ -223,6 +469,18 @@ def main() -> int:
     ap.add_argument("--served-requests", type=int, default=4000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (scale reference for PMC byte counters)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS),
+                    help="time only this workload (default tuning) and print its line")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the other full-size workloads")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time the CPU oracle on the full 2^28-pair input (minutes) and record it under profiles/")
+    ap.add_argument("--pmc-summary", metavar="WORKLOAD",
+                    help="write profiles/WORKLOAD_pmc.json from the --fetch and --write counter CSVs")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--sorts", type=int, help="sorts in the profiled run (warm-up + timed)")
+    ap.add_argument("--passes", type=int, help="passes of one sort in the profiled run")
+    ap.add_argument("--command", action="append", default=[], help="profiling command, for the record")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the sort runs on a single MI355X. Several GPUs would split the "
@@ -230,10 +488,34 @@ def main() -> int:
               "implemented, so only --gpus 1 runs", file=sys.stderr)
         return 2
 
+    if args.pmc_summary:
+        from paper_2107_01391_amd import workloads as wl
+        n = args.n if args.pmc_summary == "uniform_u32_pairs" else wl.FULL_SIZES[getattr(
+            wl, args.pmc_summary.upper())]
+        out = summarize_pmc(args.pmc_summary, args.fetch, args.write, args.sorts, args.passes, n, args.command)
+        with open(pmc_file(args.pmc_summary), "w") as f:
+            json.dump(out, f, indent=1)
+        print(json.dumps({k: out[k] for k in ("workload", "n", "sorts", "bytes_per_sort")}))
+        return 0
+
+    if args.cpu_full:
+        from paper_2107_01391_amd import workloads as wl
+        rec = cpu_full(wl.uniform_u32_pairs(FULL_N))
+        with open(CPU_FULL_FILE, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec))
+        return 0
+
     import torch
 
     from paper_2107_01391_amd import _binding as B
     from paper_2107_01391_amd import api, workloads
+
+    if args.copy_calibration:
+        calibration_copy(torch)
+    if args.workload:
+        print(json.dumps(run_workload(torch, B, api, workloads, args.workload, args.steps, args.warmup)), flush=True)
+        return 0
 
     n = args.n
     print(f"[bench] generating {n} pairs", file=sys.stderr, flush=True)
@@ -246,17 +528,6 @@ def main() -> int:
     need = B.rs_temp_bytes(desc, n, True)
     tmp = api.empty_device(need)
     stream = torch.cuda.current_stream()
-
-    if args.copy_calibration:
-        # a plain streaming kernel of known size for the PMC byte counters:
-        # reads 1 GiB and writes 1 GiB (torch's elementwise bitwise_not)
-        a = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        for _ in range(2):
-            torch.bitwise_not(a, out=b)
-        torch.cuda.synchronize()
-        del a, b
 
     def step():
         B.rs_sort_pairs(desc, keys, keys_out, vals, vals_out, n, tmp, tmp.numel(), stream)
@@ -314,6 +585,11 @@ def main() -> int:
     del keys_out, vals_out, tmp
     torch.cuda.empty_cache()
 
+    others = None
+    if not args.no_workloads:
+        others = [run_workload(torch, B, api, workloads, name, 10, 2)
+                  for name in ("uniform_decimal_u32", "fixed_point_decimals", "strings16")]
+
     batched = None
     if not args.no_batched:
         print("[bench] batched vs per-array", file=sys.stderr, flush=True)
@@ -346,7 +622,8 @@ def main() -> int:
         "config": {"workload": f"uniform_u32_pairs: {n} uint32 keys uniform over [0, 2^32), uint32 index payload, "
                                "base 256, 4 dimensions, stable ascending (rs_sort_pairs)",
                    "n": n, "passes": passes},
-        "roofline": roofline, "whole_sort": whole, "cpu_baseline": cpu, "batched_vs_per_array": batched,
+        "roofline": roofline, "whole_sort": whole, "cpu_baseline": cpu, "workloads": others,
+        "batched_vs_per_array": batched,
         "served": served, "output_check": ok, "oracle_digest_match": digest_ok,
         "device": torch.cuda.get_device_name(0),
     }

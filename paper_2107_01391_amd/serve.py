@@ -259,6 +259,14 @@ def gate(rows: list[dict], ref_rate: float = 2000.0) -> dict:
     return out
 
 
+def crossover(g: dict):
+    """The smallest p99 bound of the equal-p99 curve at which the batched
+    server's throughput exceeds the per-request server's, or None."""
+    won = [c for c in g["curve"] if c["batched_gkeys"] is not None and c["per_request_gkeys"] is not None
+           and c["batched_gkeys"] > c["per_request_gkeys"]]
+    return min(won, key=lambda c: c["p99_bound_ms"]) if won else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--rates", default="500,1000,2000,4000,8000,16000,32000,0")
@@ -267,10 +275,16 @@ def main():
     ap.add_argument("--capacity", type=int, default=1 << 29)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--min-batch", type=int, default=0, help="batched mode: fewest queued requests batched (0 = 4)")
+    ap.add_argument("--seeds", default="20210708", help="comma-separated trace seeds, one sweep each")
     a = ap.parse_args()
-    rows = sweep([float(r) for r in a.rates.split(",")], a.requests, a.warmup, a.capacity, a.streams,
-                 min_batch=a.min_batch)
-    print(json.dumps({"gate": gate(rows)}), flush=True)
+    summary = []
+    for seed in [int(x) for x in a.seeds.split(",")]:
+        rows = sweep([float(r) for r in a.rates.split(",")], a.requests, a.warmup, a.capacity, a.streams,
+                     seed=seed, min_batch=a.min_batch)
+        g = gate(rows)
+        print(json.dumps({"seed": seed, "gate": g}), flush=True)
+        summary.append({"seed": seed, "at_ref": g.get("at_ref"), "crossover": crossover(g)})
+    print(json.dumps({"summary": summary}), flush=True)
 
 
 if __name__ == "__main__":
