@@ -513,9 +513,14 @@ struct PassParams {
 // for locality: consecutive tiles run on the same XCD (workgroup b runs on
 // XCD b % 8), where the partial cache lines of neighbouring tiles' output
 // runs meet in one L2.  The grid is a multiple of 8; extra workgroups exit.
-template <typename K, class Digit, int BITS, int BLOCK, int KPT, bool PAIRS, int MODE>
-__global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit> p, const K *__restrict__ kin,
-                                                         K *__restrict__ kout, const uint32_t *__restrict__ vin,
+//
+// Keys are read as KI and written as KO, and ranked as K in between: 8-byte
+// keys whose space fits 32 bits are narrowed on their first pass's loads
+// (KI = uint64_t, K = uint32_t) and widened on their last pass's stores.
+template <typename K, class Digit, int BITS, int BLOCK, int KPT, bool PAIRS, int MODE, typename KI = K,
+          typename KO = K>
+__global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit> p, const KI *__restrict__ kin,
+                                                         KO *__restrict__ kout, const uint32_t *__restrict__ vin,
                                                          uint32_t *__restrict__ vout) {
   constexpr int WAVES = BLOCK / kWave;
   constexpr int TILE = BLOCK * KPT;
@@ -572,14 +577,14 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
   // within the tile are 32-bit)
   K k[KPT];
   uint32_t v[KPT];
-  const K *ktile = kin + elem0;
+  const KI *ktile = kin + elem0;
   const uint32_t *vtile = PAIRS ? vin + elem0 : nullptr;
   const uint32_t count = (uint32_t)(end - elem0);
   const uint32_t wfirst = wave * kWave * KPT + lane;
 #pragma unroll
   for (int r = 0; r < KPT; ++r) {
     const uint32_t e = wfirst + (uint32_t)r * kWave;
-    k[r] = e < count ? *elem32(ktile, e) : K{};
+    k[r] = e < count ? (K)*elem32(ktile, e) : K{};
     if constexpr (PAIRS) v[r] = e < count ? *elem32(vtile, e) : 0u;
   }
   if constexpr (MODE != kChained) __syncthreads();  // wcnt cleared
@@ -639,7 +644,7 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
   // ---- write keys (and values): consecutive LDS entries of one cell go
   // to consecutive output addresses; output offsets are relative to the
   // array and below 2^30
-  K *karr = kout + out_base;
+  KO *karr = kout + out_base;
   uint32_t *varr = PAIRS ? vout + out_base : nullptr;
   const uint32_t alen = (uint32_t)(limit - out_base);
 #pragma unroll
@@ -651,7 +656,7 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
       dg[r] = d;
       const uint32_t o = gdelta[d] + i;
       if (o < alen) {
-        *elem32(karr, o) = key;
+        *elem32(karr, o) = (KO)key;
         if constexpr (JOINT) *elem32(varr, o) = stage_jv[i];
       }
     }

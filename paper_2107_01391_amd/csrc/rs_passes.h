@@ -23,8 +23,10 @@ constexpr int kTilesPerHistBlockLarge = 32;
 // tables, small enough for eight workgroups per CU
 constexpr uint32_t kTileHistBudget = 24 * 1024;
 
-template <typename K, class Digit, int BITS, int BLOCK, bool SEG>
-rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const K *src, K *dst,
+// Keys are read as KI and written as KO (narrowed on a first pass, widened
+// on a last one; see rs_rank_scatter).
+template <typename K, class Digit, int BITS, int BLOCK, bool SEG, typename KI = K, typename KO = K>
+rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const KI *src, KO *dst,
                           const uint32_t *srcv, uint32_t *dstv, uint64_t n, uint64_t ntiles_bound,
                           uint32_t *table, uint32_t *sums, const TileDesc *tiles, const uint32_t *ntotal,
                           hipStream_t stream) {
@@ -46,7 +48,7 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
     th.copies = count_copies(cells * TPW, kTileHistBudget);
     const size_t lds = (size_t)TPW * th.copies * (cells + 1) * 4;
     RS_TIMED("rs_tile_histogram", stream,
-             hipLaunchKernelGGL((rs_tile_histogram<K, Digit, 256, TPW, TILE, SEG>),
+             hipLaunchKernelGGL((rs_tile_histogram<KI, Digit, 256, TPW, TILE, SEG>),
                                 dim3((uint32_t)((ntiles_bound + TPW - 1) / TPW)), dim3(256), lds, stream, th, src));
   };
   // several tiles per workgroup once there are enough tiles to fill every
@@ -85,12 +87,12 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
   const dim3 grid((uint32_t)((ntiles_bound + 7) / 8 * 8)), blk(BLOCK);
   if (pairs)
     RS_TIMED("rs_rank_scatter", stream,
-             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, BLOCK, KPT, true, MODE>), grid, blk, 0, stream, pp,
-                                src, dst, srcv, dstv));
+             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, BLOCK, KPT, true, MODE, KI, KO>), grid, blk, 0,
+                                stream, pp, src, dst, srcv, dstv));
   else
     RS_TIMED("rs_rank_scatter", stream,
-             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, BLOCK, KPT, false, MODE>), grid, blk, 0, stream, pp,
-                                src, dst, nullptr, nullptr));
+             hipLaunchKernelGGL((rs_rank_scatter<K, Digit, BITS, BLOCK, KPT, false, MODE, KI, KO>), grid, blk, 0,
+                                stream, pp, src, dst, nullptr, nullptr));
   return check_launch("rs_rank_scatter");
 }
 
@@ -140,6 +142,48 @@ rs_status prescanned_passes(const Plan &p, const Digit *digits, uint32_t P, cons
                                                                 stream);
     if (st != RS_OK) return st;
     src = dst;
+    srcv = dstv;
+  }
+  return RS_OK;
+}
+
+// Passes [0, P) over 8-byte keys whose space fits 32 bits, moved as 32-bit
+// words in between: the first pass reads the 8-byte input and writes 32-bit
+// words to a, the middle passes ping-pong between a and b, the last pass
+// writes the 8-byte output (zero-extended).  P >= 2.  Values ping-pong
+// between vals_out and alt_vals as in prescanned_passes.
+template <class Digit, int BITS, int BLOCK>
+rs_status narrowed_passes(const Plan &p, const Digit *digits, uint32_t P, const uint64_t *keys_in,
+                          uint64_t *keys_out, const uint32_t *vals_in, uint32_t *vals_out, uint32_t *a,
+                          uint32_t *b, uint32_t *alt_vals, uint64_t n, uint64_t ntiles_bound, uint32_t *table,
+                          uint32_t *sums, hipStream_t stream) {
+  const bool pairs = vals_in != nullptr;
+  uint32_t *XV = vals_out, *YV = alt_vals;
+  const uint32_t *srcv = vals_in;
+  rs_status st;
+  if (pairs && P % 2 == 1 && vals_in == vals_out) {
+    if ((st = launch_copy(YV, vals_in, n * 4, stream)) != RS_OK) return st;
+    srcv = YV;
+  }
+  const uint32_t *ksrc = nullptr;  // the 32-bit words of the previous pass
+  for (uint32_t i = 0; i < P; ++i) {
+    const bool to_x = ((P - 1 - i) % 2) == 0;
+    uint32_t *dstv = to_x ? XV : YV;
+    uint32_t *kdst = i % 2 == 0 ? a : b;
+    if (i == 0)
+      st = prescanned_pass<uint32_t, Digit, BITS, BLOCK, false, uint64_t, uint32_t>(
+          digits[i], p.pass_cells[i], pairs, keys_in, kdst, srcv, dstv, n, ntiles_bound, table, sums, nullptr,
+          nullptr, stream);
+    else if (i + 1 == P)
+      st = prescanned_pass<uint32_t, Digit, BITS, BLOCK, false, uint32_t, uint64_t>(
+          digits[i], p.pass_cells[i], pairs, ksrc, keys_out, srcv, dstv, n, ntiles_bound, table, sums, nullptr,
+          nullptr, stream);
+    else
+      st = prescanned_pass<uint32_t, Digit, BITS, BLOCK, false>(digits[i], p.pass_cells[i], pairs, ksrc, kdst, srcv,
+                                                                  dstv, n, ntiles_bound, table, sums, nullptr,
+                                                                  nullptr, stream);
+    if (st != RS_OK) return st;
+    ksrc = kdst;
     srcv = dstv;
   }
   return RS_OK;

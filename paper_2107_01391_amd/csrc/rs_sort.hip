@@ -178,48 +178,23 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   return RS_OK;
 }
 
-// 8-byte keys below 2^32 as 32-bit words, and back (zero-extended).
-static __global__ __launch_bounds__(256) void rs_narrow(const uint64_t *__restrict__ in, uint32_t *__restrict__ out,
-                                                        uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
-    out[i] = (uint32_t)in[i];
-}
-
-static __global__ __launch_bounds__(256) void rs_widen(const uint32_t *__restrict__ in, uint64_t *__restrict__ out,
-                                                       uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
-    out[i] = in[i];
-}
-
 template <typename K, class Digit, int BITS>
 static rs_status run_prescanned(const Plan &pl, const Digit *digits, const void *keys_in, void *keys_out,
                                 const uint32_t *vals_in, uint32_t *vals_out, void *tmp, hipStream_t stream) {
   char *base = (char *)tmp;
   if constexpr (sizeof(K) == 8 && !std::is_same<Digit, DigitDiv64>::value) {
     if (pl.narrow) {
-      // the passes read and write 4 bytes of key instead of 8: narrow into
-      // a, ping-pong between a and b (the alternate key array holds both),
-      // widen the last pass's array into keys_out
+      // the passes move 4 bytes of key instead of 8: the first pass reads
+      // the 8-byte keys and writes 32-bit words, the last writes 8-byte keys
+      // back; a and b (within the alternate key array) hold the words
       uint32_t *a = (uint32_t *)(base + pl.off_keys_alt);
       uint32_t *b = (uint32_t *)(base + (pl.off_keys_alt + pl.n * 4 + 255) / 256 * 256);  // within n * 8 + 256
-      uint64_t blocks = (pl.n + 255) / 256;
-      if (blocks > (uint64_t)cu_count() * 16) blocks = (uint64_t)cu_count() * 16;
-      RS_TIMED("rs_narrow", stream, hipLaunchKernelGGL(rs_narrow, dim3((uint32_t)blocks), dim3(256), 0, stream,
-                                                       (const uint64_t *)keys_in, a, pl.n));
-      rs_status st = check_launch("rs_narrow");
-      if (st != RS_OK) return st;
-      const bool odd = pl.npasses % 2 == 1;
-      uint32_t *last = odd ? b : a;
-      st = with_block<uint32_t, BITS>(pl.block, [&]<int BLOCK>() {
-        return prescanned_passes<uint32_t, Digit, BITS, BLOCK, false>(
-            pl, digits, pl.npasses, a, last, vals_in, vals_out, odd ? a : b,
+      return with_block<uint32_t, BITS>(pl.block, [&]<int BLOCK>() {
+        return narrowed_passes<Digit, BITS, BLOCK>(
+            pl, digits, pl.npasses, (const uint64_t *)keys_in, (uint64_t *)keys_out, vals_in, vals_out, a, b,
             pl.pairs ? (uint32_t *)(base + pl.off_vals_alt) : nullptr, pl.n, pl.ntiles,
-            (uint32_t *)(base + pl.off_table), (uint32_t *)(base + pl.off_sums), nullptr, nullptr, stream);
+            (uint32_t *)(base + pl.off_table), (uint32_t *)(base + pl.off_sums), stream);
       });
-      if (st != RS_OK) return st;
-      RS_TIMED("rs_widen", stream, hipLaunchKernelGGL(rs_widen, dim3((uint32_t)blocks), dim3(256), 0, stream, last,
-                                                      (uint64_t *)keys_out, pl.n));
-      return check_launch("rs_widen");
     }
   }
   return with_block<K, BITS>(pl.block, [&]<int BLOCK>() {
