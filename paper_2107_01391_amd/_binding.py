@@ -33,7 +33,7 @@ EXPORTED = ["rs_temp_bytes", "rs_sort_keys", "rs_sort_pairs", "rs_sort_pairs_noa
             "rs_graph_sort", "rs_graph_sort_batched", "rs_graph_launch", "rs_graph_destroy",
             "rs_server_work_bytes", "rs_server_create", "rs_server_submit", "rs_server_poll", "rs_server_wait",
             "rs_server_result", "rs_server_release", "rs_server_get_stats", "rs_server_reset_stats",
-            "rs_server_clock", "rs_server_destroy", "rs_server_collect"]
+            "rs_server_clock", "rs_server_destroy", "rs_server_collect", "rs_plan_inspect"]
 RS_ERR_BUSY = 8
 RS_SERVE_BATCHED, RS_SERVE_PER_REQUEST = 0, 1
 
@@ -62,6 +62,22 @@ class Tuning(ctypes.Structure):
     """rs_tuning: how the digits are grouped into passes and the tile shape."""
     _fields_ = [("digit_bits", ctypes.c_uint32), ("max_cells", ctypes.c_uint32), ("tile_block", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32), ("prescan_min_n", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+RS_FORM_LOCAL, RS_FORM_LITERAL, RS_FORM_CHAINED, RS_FORM_PRESCANNED = 0, 1, 2, 3
+
+
+class PlanInfo(ctypes.Structure):
+    """rs_plan_info: the form a sort takes and, for the literal form, where
+    its counts, traverse maps and starts lie in tmp."""
+    _fields_ = [("form", ctypes.c_uint32), ("passes", ctypes.c_uint32), ("tile_keys", ctypes.c_uint32),
+                ("literal_cells", ctypes.c_uint32), ("map_rows", ctypes.c_uint32), ("map_inner", ctypes.c_uint32),
+                ("scan_chunk", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("off_counts", ctypes.c_uint64),
+                ("off_map_lo", ctypes.c_uint64), ("off_map_hi", ctypes.c_uint64), ("off_starts", ctypes.c_uint64),
+                ("tmp_bytes", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
@@ -152,6 +168,8 @@ def load_library(path: str | None = None):
               "rs_server_result", "rs_server_release", "rs_server_get_stats", "rs_server_reset_stats",
               "rs_server_clock", "rs_server_destroy", "rs_server_collect"):
         getattr(lib, f).restype = ctypes.c_int
+    lib.rs_plan_inspect.argtypes = [dp, u64, ci, ctypes.POINTER(PlanInfo)]
+    lib.rs_plan_inspect.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -209,6 +227,12 @@ def rs_sort_pairs_noalloc(desc: KeyDesc, keys_in, keys_out, vals_in, vals_out, n
     """rs_sort_pairs with the library's static device scratch (no tmp)."""
     _check(load_library().rs_sort_pairs_noalloc(ctypes.byref(desc), _ptr(keys_in), _ptr(keys_out), _ptr(vals_in),
                                                 _ptr(vals_out), n, _stream(stream)))
+
+
+def rs_plan_inspect(desc: KeyDesc, n: int, with_values: bool) -> PlanInfo:
+    info = PlanInfo()
+    _check(load_library().rs_plan_inspect(ctypes.byref(desc), n, int(bool(with_values)), ctypes.byref(info)))
+    return info
 
 
 def rs_batched_temp_bytes(desc: KeyDesc, total: int, nseg: int, with_values: bool) -> int:

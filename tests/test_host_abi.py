@@ -304,3 +304,31 @@ def test_noalloc_sort_checks_before_any_device_call():
     assert B.rs_temp_bytes(d, too_big, True) > B.RS_NOALLOC_SCRATCH_BYTES
     assert lib.rs_sort_pairs_noalloc(ctypes.byref(d), fake, fake, fake, fake, too_big, None) == 5
     assert "static scratch" in B.rs_last_error()
+
+
+@pytest.mark.parametrize("kind,base,ndims,n,pairs,form", [
+    ("u32", 10, 6, 10**6, False, B.RS_FORM_LITERAL),      # the 10^6-cell decimal space, keys only
+    ("u32", 10, 6, 10**6, True, B.RS_FORM_CHAINED),       # with values: grouped passes
+    ("u32", 256, 4, 1 << 28, True, B.RS_FORM_PRESCANNED),
+    ("u32", 256, 4, 4096, True, B.RS_FORM_LOCAL),
+    ("u32", 1000, 2, 300_000, False, B.RS_FORM_LITERAL),  # two dimensions: 1000 rows of 1000 cells
+    ("u32", 60_000, 1, 70_000, False, B.RS_FORM_LITERAL),  # one dimension: one row
+])
+def test_plan_inspect_forms_and_literal_layout(kind, base, ndims, n, pairs, form):
+    d = B.key_desc(kind, base=base, ndims=ndims)
+    info = B.rs_plan_inspect(d, n, pairs)
+    assert info.form == form
+    assert info.tmp_bytes == B.rs_temp_bytes(d, n, pairs)
+    if form != B.RS_FORM_LITERAL:
+        assert info.passes >= 1 and info.literal_cells == 0
+        return
+    cells = base ** ndims
+    assert info.literal_cells == cells and info.passes == 0
+    assert info.map_rows == (base if ndims >= 2 else 1)
+    assert info.map_rows * info.map_inner == cells
+    # counts, maps and starts lie inside tmp and do not overlap
+    spans = sorted([(info.off_counts, cells * 4), (info.off_map_lo, info.map_rows * 4),
+                    (info.off_map_hi, info.map_rows * 4), (info.off_starts, cells * 4)])
+    for (a, la), (b, _) in zip(spans, spans[1:]):
+        assert a + la <= b
+    assert spans[-1][0] + spans[-1][1] <= info.tmp_bytes
