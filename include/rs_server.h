@@ -23,8 +23,10 @@
  *     streams, a request of more than batch_max_n keys at the head runs
  *     alone and only the small requests at the head are batched, so small
  *     requests do not wait for a large one's sort; with a longer queue
- *     everything is batched.  Fewer than min_batch requests run as
- *     single-array sorts, so light load costs what the baseline does.
+ *     everything is batched.  With fewer than min_batch small requests at
+ *     the head, the head alone is dispatched as a single-array sort (the
+ *     others go to other idle streams), so light load runs as the
+ *     baseline does.
  *   - RS_SERVE_PER_REQUEST: one rs_sort_pairs / rs_sort_keys launch per
  *     request (the baseline).
  *   - With streams > 1, launches overlap on the device.
@@ -65,8 +67,8 @@ typedef struct rs_server_config {
   uint32_t streams;      /* launches in flight at once, 1..8 */
   uint32_t mode;         /* RS_SERVE_BATCHED or RS_SERVE_PER_REQUEST */
   uint32_t with_values;  /* requests carry uint32 values */
-  uint32_t min_batch;    /* batched mode: fewer queued requests than this run as single-array sorts
-                            in one launch slot (0 = 4) */
+  uint32_t min_batch;    /* batched mode: fewest small requests at the head of the queue that are
+                            batched; with fewer, the head is dispatched alone (0 = 4) */
   uint64_t batch_max_n;  /* batched mode, short queue: requests of more keys run alone (0 = 2^20) */
 } rs_server_config;
 

@@ -285,7 +285,17 @@ struct rs_server {
       const bool backlog = queue.size() > cfg.streams;
       const uint64_t big = backlog ? ~0ull : (cfg.batch_max_n ? cfg.batch_max_n : (1ull << 20));
       const bool alone = cfg.mode == RS_SERVE_PER_REQUEST || reqs[queue.front()].n > big;
-      const uint32_t take = alone ? 1u : batch_cap(&cfg);
+      uint32_t take = alone ? 1u : batch_cap(&cfg);
+      if (!alone) {
+        // fewer than min_batch small requests at the head: dispatch the head
+        // alone, as the per-request server does, so that the others go to
+        // the other idle streams instead of running one after another in
+        // this launch
+        const uint32_t min_batch = cfg.min_batch ? cfg.min_batch : 4;
+        uint32_t run = 0;
+        for (auto it = queue.begin(); it != queue.end() && run < min_batch && reqs[*it].n <= big; ++it) ++run;
+        if (run < min_batch) take = 1;
+      }
       std::vector<uint64_t> tickets;
       std::vector<Span> spans;
       while (!queue.empty() && tickets.size() < take) {
