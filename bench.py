@@ -235,7 +235,8 @@ def calibration_copy(torch) -> None:
 
 
 PROF_KERNELS = ("rs_tile_histogram", "rs_cell_scan", "rs_rank_scatter", "rs_digit_hash_histogram", "rs_fill",
-                "rs_cell_count", "rs_cell_emit", "rs_small_sort", "rs_copy")
+                "rs_cell_count", "rs_cell_emit", "rs_small_sort", "rs_copy", "rs_str_bucket_count",
+                "rs_str_bucket_sort", "rs_seg_plan", "rs_seg_tiles")
 
 
 def run_workload(torch, B, api, workloads, name: str, steps: int, warmup: int) -> dict:

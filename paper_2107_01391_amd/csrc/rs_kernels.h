@@ -524,7 +524,10 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
                                                          uint32_t *__restrict__ vout) {
   constexpr int WAVES = BLOCK / kWave;
   constexpr int TILE = BLOCK * KPT;
-  constexpr int BINS = 1 << BITS;
+  // cells of one pass: 2^BITS, except base-27 string pairs of symbols (the
+  // only 16-byte passes of 10 bits), whose 729 cells need 736 table words
+  // (a smaller table leaves room for one more workgroup per CU)
+  constexpr int BINS = (sizeof(K) >= 16 && BITS == 10) ? 736 : (1 << BITS);
   constexpr int CPT = (BINS + BLOCK - 1) / BLOCK;  // cells per thread
   constexpr int STAGE = TILE * (sizeof(K) > 4 ? (int)sizeof(K) : 4);
   // Values get their own staging (keys and values written in one sweep)

@@ -17,8 +17,6 @@
 
 namespace rs {
 
-constexpr int kTilesPerHistBlock = 8;
-constexpr int kTilesPerHistBlockLarge = 32;
 // LDS of the per-tile count tables: two lane-group copies of eight 256-cell
 // tables, small enough for eight workgroups per CU
 constexpr uint32_t kTileHistBudget = 24 * 1024;
@@ -52,11 +50,14 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
                                 dim3((uint32_t)((ntiles_bound + TPW - 1) / TPW)), dim3(256), lds, stream, th, src));
   };
   // several tiles per workgroup once there are enough tiles to fill every
-  // CU with them (each workgroup then writes longer runs of the cell-major
-  // table: 32 tiles make 128-byte runs, one table copy of 256 cells per
-  // tile in LDS); one tile each below that
-  if (cells <= 256 && ntiles_bound >= (uint64_t)cu_count() * 64) histogram.template operator()<kTilesPerHistBlockLarge>();
-  else if (ntiles_bound >= (uint64_t)cu_count() * 32) histogram.template operator()<kTilesPerHistBlock>();
+  // CU with them: each workgroup then writes runs of TPW entries of the
+  // cell-major table instead of single words (32 tiles of 256 cells make
+  // 128-byte runs with one table copy per tile in LDS; wider tables keep 8
+  // tiles, so that at least four workgroups per CU stay in flight); one
+  // tile each below that
+  const uint64_t many = (uint64_t)cu_count() * 32;
+  if (cells <= 256 && ntiles_bound >= 2 * many) histogram.template operator()<32>();
+  else if (ntiles_bound >= many) histogram.template operator()<8>();
   else histogram.template operator()<1>();
   if ((st = check_launch("rs_tile_histogram")) != RS_OK) return st;
 

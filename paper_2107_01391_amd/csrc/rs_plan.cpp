@@ -210,6 +210,11 @@ static rs_status plan_passes(const KeyInfo &k, const Tuning &tune, Plan &p, std:
     *why = "a pass with more than 2048 cells is not supported";
     return RS_ERR_UNSUPPORTED;
   }
+  if (p.mode == kModeStr16 && p.bits == 10 && p.bins > 736) {
+    // the 16-byte scatter sizes its tables for base-27 symbol pairs
+    *why = "string passes of more than 736 cells are not supported";
+    return RS_ERR_UNSUPPORTED;
+  }
 
   if ((size_t)p.npasses * p.bins * 4 > 64 * 1024) {
     *why = "the passes' count tables exceed 64 KiB of LDS";
@@ -307,6 +312,22 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     p.scan_chunks = (uint32_t)((entries + kBigScanChunk - 1) / kBigScanChunk);
     p.off_table = take(entries * 4);
     p.off_sums = take((size_t)p.scan_chunks * 4);
+    if (p.mode == kModeStr16 && k.base == 27 && k.ndims == 16 && p.npasses == 8 && n >= kStrBucketMinN) {
+      // 27^4 buckets of the four leading symbols; at most n / 65 of them
+      // hold more than 64 keys (the ones a wave cannot sort)
+      const uint64_t cells = 27ull * 27 * 27 * 27;
+      p.str_buckets = true;
+      p.off_bcounts = take(cells * 4);
+      p.off_bctrl = take(4);
+      p.bfill_bytes = off - p.off_bcounts;
+      p.off_bstarts = take(cells * 4);
+      p.off_bsums = take((cells + kBigScanChunk - 1) / kBigScanChunk * 4);
+      p.blist_cap = (uint32_t)(n / 65 + 1);
+      p.off_blist = take((size_t)p.blist_cap * 16);
+      rs_status sst = make_seg_layout(p, 6, n, n, p.blist_cap, false, 256, &p.bseg, why);
+      if (sst != RS_OK) return sst;
+      p.off_bseg = take(p.bseg.bytes);
+    }
   } else {
     p.off_keys_alt = take((size_t)n * k.key_bytes);
     if (pairs) p.off_vals_alt = take((size_t)n * 4);

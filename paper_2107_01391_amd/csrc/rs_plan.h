@@ -101,6 +101,16 @@ struct Plan {
   size_t off_table = 0, off_sums = 0;  // prescanned: per-tile counts, chunk sums
   uint32_t scan_chunks = 0;            // chunks of the cell scan
   SegLayout seg;                       // batched form
+  // base-27 16-symbol strings, prescanned: the passes over the four leading
+  // symbols, then every bucket of equal leading symbols sorted on its own
+  // (rs_str_buckets.h); long buckets of distinct keys go through the
+  // batched passes over the other twelve symbols (layout bseg, sized for
+  // blist_cap buckets, at off_bseg; it reuses the alternate arrays)
+  bool str_buckets = false;
+  size_t off_bcounts = 0, off_bctrl = 0, off_bstarts = 0, off_bsums = 0, off_blist = 0, off_bseg = 0;
+  size_t bfill_bytes = 0;              // counts and control words, cleared together
+  uint32_t blist_cap = 0;
+  SegLayout bseg;
   size_t total = 0;
 };
 
@@ -122,5 +132,8 @@ constexpr uint32_t kBigScanChunk = kScanBlock * kBigScanItems;
 constexpr uint32_t kLiteralMaxCells = 1u << 24;
 // Longest array one workgroup sorts whole on chip (256 threads x 16 keys).
 constexpr uint64_t kLocalMaxN = 4096;
+// Base-27 strings from this many keys sort by buckets of their four leading
+// symbols (fewer passes over HBM); shorter arrays run all eight passes.
+constexpr uint64_t kStrBucketMinN = 1ull << 20;
 
 }  // namespace rs

@@ -28,6 +28,8 @@
 #include "rs_kernels.h"
 #include "rs_passes.h"
 #include "rs_seg_kernels.h"
+#include "rs_segmented.h"
+#include "rs_str_buckets.h"
 
 namespace rs {
 
@@ -178,10 +180,108 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   return RS_OK;
 }
 
+// Base-27 strings of 16 symbols by buckets (rs_str_buckets.h): the two
+// passes over the four leading symbols order the array by its 27^4 leading
+// cells; each cell's bucket is then sorted by the twelve other symbols, in
+// place in the output.  Long buckets of distinct keys, if any, are listed on
+// the device; the list's length is read back (the one synchronisation of
+// this form) and they go through the batched passes over the twelve
+// symbols.
+static rs_status run_str_buckets(const Plan &pl, const void *keys_in, void *keys_out, const uint32_t *vals_in,
+                                 uint32_t *vals_out, void *tmp, hipStream_t stream) {
+  char *base = (char *)tmp;
+  const bool pairs = pl.pairs;
+  Str16 *X = (Str16 *)keys_out;
+  Str16 *Y = (Str16 *)(base + pl.off_keys_alt);
+  uint32_t *YV = pairs ? (uint32_t *)(base + pl.off_vals_alt) : nullptr;
+  uint32_t *table = (uint32_t *)(base + pl.off_table), *sums = (uint32_t *)(base + pl.off_sums);
+  // passes 6 (symbols 2, 3) and 7 (symbols 0, 1) of the least-significant-
+  // first order: keys_in -> Y -> X
+  rs_status st = prescanned_pass<Str16, DigitStr16, 10, 256, false>(
+      pl.s16[6], pl.pass_cells[6], pairs, (const Str16 *)keys_in, Y, vals_in, YV, pl.n, pl.ntiles, table, sums,
+      nullptr, nullptr, stream);
+  if (st != RS_OK) return st;
+  st = prescanned_pass<Str16, DigitStr16, 10, 256, false>(pl.s16[7], pl.pass_cells[7], pairs, Y, X, YV, vals_out,
+                                                          pl.n, pl.ntiles, table, sums, nullptr, nullptr, stream);
+  if (st != RS_OK) return st;
+
+  // S of the four leading symbols, and each bucket's start
+  StrBucketParams q;
+  memset(&q, 0, sizeof q);
+  q.lead.pos = 0;
+  q.lead.width = 4;
+  q.lead.base = 27;
+  q.lead.cx = pl.key.descending ? ~0u : 0u;
+  q.lead.ca = pl.key.descending ? kStrBucketCells : 0u;
+  q.n = pl.n;
+  q.counts = (uint32_t *)(base + pl.off_bcounts);
+  q.starts = (uint32_t *)(base + pl.off_bstarts);
+  q.list = (uint64_t *)(base + pl.off_blist);
+  q.list_count = (uint32_t *)(base + pl.off_bctrl);
+  q.list_cap = pl.blist_cap;
+  q.descending = pl.key.descending ? 1u : 0u;
+  if ((st = launch_fill(q.counts, pl.bfill_bytes, 0, stream)) != RS_OK) return st;
+  uint64_t grid = (pl.n + 255) / 256;
+  if (grid > (uint64_t)cu_count() * 16) grid = (uint64_t)cu_count() * 16;
+  RS_TIMED("rs_str_bucket_count", stream,
+           hipLaunchKernelGGL((rs_str_bucket_count<256>), dim3((uint32_t)grid), dim3(256), 0, stream, q, X));
+  if ((st = check_launch("rs_str_bucket_count")) != RS_OK) return st;
+  const uint64_t cells = kStrBucketCells;
+  const uint32_t nchunks = (uint32_t)((cells + kBigScanChunk - 1) / kBigScanChunk);
+  uint32_t *bsums = (uint32_t *)(base + pl.off_bsums);
+  RowMaps nomaps;
+  memset(&nomaps, 0, sizeof nomaps);
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan_reduce<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
+                              stream, q.counts, cells, nullptr, 1, bsums, nomaps));
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan_spine<1024, kBigScanChunk>), dim3(1), dim3(1024), 0, stream, bsums,
+                              cells, nullptr, 1));
+  RS_TIMED("rs_cell_scan", stream,
+           hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
+                              stream, q.counts, cells, nullptr, 1, bsums, (uint32_t *)q.starts, nomaps));
+  if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
+
+  // every bucket, one wave each
+  const uint32_t sgrid = (uint32_t)cu_count() * 8;
+  if (pairs)
+    RS_TIMED("rs_str_bucket_sort", stream,
+             hipLaunchKernelGGL((rs_str_bucket_sort<256, true>), dim3(sgrid), dim3(256), 0, stream, q, X, vals_out));
+  else
+    RS_TIMED("rs_str_bucket_sort", stream,
+             hipLaunchKernelGGL((rs_str_bucket_sort<256, false>), dim3(sgrid), dim3(256), 0, stream, q, X, nullptr));
+  if ((st = check_launch("rs_str_bucket_sort")) != RS_OK) return st;
+
+  uint32_t nlong = 0;
+  if (hipMemcpyAsync(&nlong, q.list_count, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return fail(RS_ERR_HIP, "reading the count of long buckets");
+  if (nlong == 0) return RS_OK;
+  if (nlong > pl.blist_cap) return fail(RS_ERR_HIP, "long-bucket list overflow");
+  // the long buckets of distinct keys: the batched passes over the twelve
+  // symbols, in place, with the alternate arrays as their scratch
+  SegLayout L;
+  std::string why;
+  if ((st = make_seg_layout(pl, 6, pl.n, pl.n, nlong, false, 256, &L, &why)) != RS_OK) return fail(st, why);
+  if (L.bytes > pl.bseg.bytes) return fail(RS_ERR_HIP, "long-bucket layout exceeds its scratch");
+  return run_segmented<Str16, DigitStr16, 10>(pl, L, pl.s16, X, X, pairs ? vals_out : nullptr,
+                                              pairs ? vals_out : nullptr, Y, YV, q.list, q.list + pl.blist_cap,
+                                              base + pl.off_bseg, stream);
+}
+
 template <typename K, class Digit, int BITS>
 static rs_status run_prescanned(const Plan &pl, const Digit *digits, const void *keys_in, void *keys_out,
                                 const uint32_t *vals_in, uint32_t *vals_out, void *tmp, hipStream_t stream) {
   char *base = (char *)tmp;
+  if constexpr (std::is_same<K, Str16>::value && BITS == 10) {
+    if (pl.str_buckets) {
+      hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+      // a captured sequence cannot wait for the long-bucket count: all
+      // eight passes then
+      if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap == hipStreamCaptureStatusNone)
+        return run_str_buckets(pl, keys_in, keys_out, vals_in, vals_out, tmp, stream);
+    }
+  }
   if constexpr (sizeof(K) == 8 && !std::is_same<Digit, DigitDiv64>::value) {
     if (pl.narrow) {
       // the passes move 4 bytes of key instead of 8: the first pass reads

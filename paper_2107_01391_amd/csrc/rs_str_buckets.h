@@ -1,0 +1,168 @@
+// rs_str_buckets.h -- the bucket hierarchy for base-27 strings of 16 symbols
+// (Section 2.2's independent buckets, applied to the dimension groups of
+// Section 3.1.1): after the passes over the four leading symbols the array
+// is in order of its 27^4 leading cells, and every cell's keys form one
+// contiguous bucket in input order.  Each bucket is then sorted on its own
+// by the twelve remaining symbols:
+//
+//   rs_str_bucket_count  S[cell] for the leading four symbols (the hashing
+//                        cycle of that group, eq. (1)), counted over the
+//                        already ordered array with one atomic per run of
+//                        equal cells in a wave
+//   (the cell scan)      each bucket's start: the walk's running position
+//   rs_str_bucket_sort   one wave per bucket: a bucket of at most 64 keys is
+//                        ranked in registers and written back in place; a
+//                        bucket whose keys agree on all twelve symbols is
+//                        already in order; any other bucket is listed for
+//                        the batched passes over the twelve symbols
+//
+// A wave ranks its bucket by the twelve symbols as one 60-bit code (5 bits
+// per symbol, most significant first, order-preserving because every symbol
+// is below 32): rank = keys with a smaller code + keys with an equal code in
+// earlier lanes (lanes hold the bucket in input order), found from one
+// ballot per code bit, most significant first, stopping once no group of
+// equal-so-far lanes can split any more.  That is the stable counting sort's
+// placement (Section 2.3) over the 64 keys, with the cell order taken bit by
+// bit.
+#pragma once
+
+#include "rs_kernels.h"
+
+namespace rs {
+
+// 27^4 cells of the four leading symbols.
+constexpr uint32_t kStrBucketCells = 27u * 27u * 27u * 27u;
+// Longest bucket a single wave sorts.
+constexpr uint32_t kStrWaveBucket = 64;
+
+// Symbol of byte b: pad (0) -> 0, 'a'..'z' -> 1..26, anything else clamped
+// to 26 (invalid input, as the passes' codec clamps it).
+__device__ __forceinline__ uint32_t str27_symbol(uint32_t b) { return b ? (b - 96u < 26u ? b - 96u : 26u) : 0u; }
+
+// The twelve trailing symbols (positions 4..15) as a 60-bit code; ~code
+// (within 60 bits) for descending order.
+__device__ __forceinline__ uint64_t str27_rest_code(const Str16 &k, bool descending) {
+  uint64_t code = 0;
+#pragma unroll
+  for (int j = 4; j < 16; ++j) {
+    const uint32_t b = (k.w[j / 4] >> (8 * (j % 4))) & 0xffu;
+    code = code << 5 | str27_symbol(b);
+  }
+  return descending ? (~code & ((1ull << 60) - 1)) : code;
+}
+
+struct StrBucketParams {
+  DigitStr16 lead;        // cell of the four leading symbols, as the passes order them
+  uint64_t n;
+  uint32_t *counts;       // [kStrBucketCells], zero before the count kernel
+  const uint32_t *starts; // [kStrBucketCells] exclusive scan of counts
+  uint64_t *list;         // buckets for the batched passes: lo[cap], then hi[cap]
+  uint32_t *list_count;   // zero before the sort kernel; may exceed cap only if n does
+  uint32_t list_cap;
+  uint32_t descending;
+};
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void rs_str_bucket_count(const StrBucketParams q, const Str16 *__restrict__ keys) {
+  const uint32_t lane = lane_id();
+  for (uint64_t base = (uint64_t)blockIdx.x * BLOCK; base < q.n; base += (uint64_t)gridDim.x * BLOCK) {
+    const uint64_t e = base + threadIdx.x;
+    const bool valid = e < q.n;
+    const uint32_t c = valid ? q.lead(keys[e]) : 0u;
+    const uint32_t prev = __shfl_up(c, 1, kWave);
+    const bool head = valid && (lane == 0 || prev != c);
+    const uint64_t heads = ballot(head);
+    const uint64_t live = ballot(valid);
+    if (head) {
+      // the run ends at the next head, or at the wave's last valid lane
+      const uint64_t later = lane == 63 ? 0ull : heads & (~0ull << (lane + 1));
+      const uint32_t end = later ? (uint32_t)__builtin_ctzll(later) : 64u - (uint32_t)__builtin_clzll(live);
+      if (c < kStrBucketCells) atomicAdd(q.counts + c, end - lane);
+    }
+  }
+}
+
+template <int BLOCK, bool PAIRS>
+__global__ __launch_bounds__(BLOCK) void rs_str_bucket_sort(const StrBucketParams q, Str16 *__restrict__ keys,
+                                                            uint32_t *__restrict__ vals) {
+  const uint32_t lane = lane_id();
+  const uint32_t waves = gridDim.x * (BLOCK / kWave);
+  const bool desc = q.descending != 0;
+  // each wave takes 64 cells at a time: their counts and starts in one
+  // load, then the buckets of more than one key one after another
+  for (uint32_t c0 = (blockIdx.x * (BLOCK / kWave) + threadIdx.x / kWave) * kWave; c0 < kStrBucketCells;
+       c0 += waves * kWave) {
+    const uint32_t c = c0 + lane;
+    const uint32_t cnt_l = c < kStrBucketCells ? q.counts[c] : 0u;
+    const uint32_t s_l = c < kStrBucketCells ? q.starts[c] : 0u;
+    uint64_t todo = ballot(cnt_l > 1);
+    while (todo) {
+      const int j = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const uint32_t cnt = __builtin_amdgcn_readlane(cnt_l, j);
+      const uint64_t s = __builtin_amdgcn_readlane(s_l, j);
+      if (s + cnt > q.n) continue;  // never, for counts of this array
+      if (cnt <= kStrWaveBucket) {
+        const bool valid = lane < cnt;
+        Str16 k{};
+        uint32_t v = 0;
+        if (valid) {
+          k = keys[s + lane];
+          if constexpr (PAIRS) v = vals[s + lane];
+        }
+        const uint64_t code = str27_rest_code(k, desc);
+        const uint64_t active = ballot(valid);
+        uint64_t eq = active, lt = 0;
+        for (int b = 59; b >= 0; --b) {
+          const bool bit = (code >> b) & 1u;
+          const uint64_t B = ballot(valid && bit);
+          if (B != 0 && B != active) {  // uniform; otherwise no lane's sets change
+            if (bit) {
+              lt |= eq & ~B;
+              eq &= B;
+            } else {
+              eq &= ~B;
+            }
+          }
+          // after each symbol: stop once, within every group of lanes equal
+          // so far, the bits still to come agree too (the groups can no
+          // longer split, so no rank can change)
+          if (b % 5 == 0 && b > 0) {
+            const uint64_t rest = code & ((1ull << b) - 1);
+            const int leader = valid ? __builtin_ctzll(eq) : (int)lane;
+            const uint64_t lead_rest = __shfl(rest, leader, kWave);
+            if (ballot(valid && rest != lead_rest) == 0) break;
+          }
+        }
+        const uint32_t rank = (uint32_t)__builtin_popcountll(lt) + count_below(eq);
+        if (valid) {
+          keys[s + rank] = k;
+          if constexpr (PAIRS) vals[s + rank] = v;
+        }
+      } else {
+        // a long bucket: already in order when its keys agree on the twelve
+        // symbols (the input order is the order of equal keys)
+        uint64_t lo = ~0ull, hi = 0;
+        for (uint32_t i = lane; i < cnt; i += kWave) {
+          const uint64_t code = str27_rest_code(keys[s + i], false);
+          lo = code < lo ? code : lo;
+          hi = code > hi ? code : hi;
+        }
+        for (int o = kWave / 2; o > 0; o >>= 1) {  // every lane holds at least one key
+          const uint64_t l2 = __shfl_xor(lo, o, kWave), h2 = __shfl_xor(hi, o, kWave);
+          lo = l2 < lo ? l2 : lo;
+          hi = h2 > hi ? h2 : hi;
+        }
+        if (lo != hi && lane == 0) {
+          const uint32_t at = atomicAdd(q.list_count, 1u);
+          if (at < q.list_cap) {
+            q.list[at] = s;
+            q.list[q.list_cap + at] = s + cnt;
+          }
+        }
+      }
+    }
+  }
+}
+
+}  // namespace rs
