@@ -28,7 +28,13 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls are asynchronous: they enqueue kernels and return.  Errors found
  *     before launching are returned; faults during execution surface at the
- *     caller's next synchronisation.
+ *     caller's next synchronisation.  Two exceptions wait on the stream:
+ *     RS_FLAG_VALIDATE, and rs_sort_keys / rs_sort_pairs of base-27 strings
+ *     of 16 symbols from 2^21 keys (the prescanned passes), which sort the
+ *     buckets of the four leading symbols one by one and read back how many
+ *     long buckets of distinct keys need the batched passes.  While the
+ *     stream is being captured those strings run all eight passes instead,
+ *     with no wait.
  *   - Order is ascending and stable: equal keys keep their input order
  *     (Section 1's definition of a stable sort; the position arithmetic of
  *     counting sort, Section 2.3).
