@@ -10,11 +10,12 @@
 //                        already ordered array with one atomic per run of
 //                        equal cells in a wave
 //   (the cell scan)      each bucket's start: the walk's running position
-//   rs_str_bucket_sort   one wave per bucket: a bucket of at most 64 keys is
-//                        ranked in registers and written back in place; a
-//                        bucket whose keys agree on all twelve symbols is
-//                        already in order; any other bucket is listed for
-//                        the batched passes over the twelve symbols
+//   rs_str_bucket_sort   buckets of at most 64 keys packed into the 64 lanes
+//                        of a wave, ranked in registers and written back in
+//                        place; a longer bucket whose keys agree on all
+//                        twelve symbols is already in order; any other is
+//                        listed for the batched passes over the twelve
+//                        symbols
 //
 // A wave ranks its bucket by the twelve symbols as one 60-bit code (5 bits
 // per symbol, most significant first, order-preserving because every symbol
@@ -85,81 +86,107 @@ __global__ __launch_bounds__(BLOCK) void rs_str_bucket_count(const StrBucketPara
 template <int BLOCK, bool PAIRS>
 __global__ __launch_bounds__(BLOCK) void rs_str_bucket_sort(const StrBucketParams q, Str16 *__restrict__ keys,
                                                             uint32_t *__restrict__ vals) {
-  const uint32_t lane = lane_id();
-  const uint32_t waves = gridDim.x * (BLOCK / kWave);
+  constexpr int WPB = BLOCK / kWave;
+  // per wave: the buckets packed into its 64 lanes (start, first lane, keys)
+  __shared__ uint32_t slot_s[WPB][kWave], slot_off[WPB][kWave], slot_cnt[WPB][kWave];
+  const uint32_t lane = lane_id(), wv = threadIdx.x / kWave;
+  const uint32_t waves = gridDim.x * WPB;
   const bool desc = q.descending != 0;
   // each wave takes 64 cells at a time: their counts and starts in one
-  // load, then the buckets of more than one key one after another
-  for (uint32_t c0 = (blockIdx.x * (BLOCK / kWave) + threadIdx.x / kWave) * kWave; c0 < kStrBucketCells;
-       c0 += waves * kWave) {
+  // load, then their buckets in cell order
+  for (uint32_t c0 = (blockIdx.x * WPB + wv) * kWave; c0 < kStrBucketCells; c0 += waves * kWave) {
     const uint32_t c = c0 + lane;
     const uint32_t cnt_l = c < kStrBucketCells ? q.counts[c] : 0u;
     const uint32_t s_l = c < kStrBucketCells ? q.starts[c] : 0u;
-    uint64_t todo = ballot(cnt_l > 1);
-    while (todo) {
-      const int j = __builtin_ctzll(todo);
-      todo &= todo - 1;
+    const bool sane = (uint64_t)s_l + cnt_l <= q.n;  // always, for counts of this array
+
+    // long buckets: already in order when their keys agree on the twelve
+    // symbols (the input order is the order of equal keys); else listed
+    uint64_t longs = ballot(sane && cnt_l > kStrWaveBucket);
+    while (longs) {
+      const int j = __builtin_ctzll(longs);
+      longs &= longs - 1;
       const uint32_t cnt = __builtin_amdgcn_readlane(cnt_l, j);
       const uint64_t s = __builtin_amdgcn_readlane(s_l, j);
-      if (s + cnt > q.n) continue;  // never, for counts of this array
-      if (cnt <= kStrWaveBucket) {
-        const bool valid = lane < cnt;
-        Str16 k{};
-        uint32_t v = 0;
-        if (valid) {
-          k = keys[s + lane];
-          if constexpr (PAIRS) v = vals[s + lane];
+      uint64_t lo = ~0ull, hi = 0;
+      for (uint32_t i = lane; i < cnt; i += kWave) {
+        const uint64_t code = str27_rest_code(keys[s + i], false);
+        lo = code < lo ? code : lo;
+        hi = code > hi ? code : hi;
+      }
+      for (int o = kWave / 2; o > 0; o >>= 1) {  // every lane holds at least one key
+        const uint64_t l2 = __shfl_xor(lo, o, kWave), h2 = __shfl_xor(hi, o, kWave);
+        lo = l2 < lo ? l2 : lo;
+        hi = h2 > hi ? h2 : hi;
+      }
+      if (lo != hi && lane == 0) {
+        const uint32_t at = atomicAdd(q.list_count, 1u);
+        if (at < q.list_cap) {
+          q.list[at] = s;
+          q.list[q.list_cap + at] = s + cnt;
         }
-        const uint64_t code = str27_rest_code(k, desc);
-        const uint64_t active = ballot(valid);
-        uint64_t eq = active, lt = 0;
-        for (int b = 59; b >= 0; --b) {
-          const bool bit = (code >> b) & 1u;
-          const uint64_t B = ballot(valid && bit);
-          if (B != 0 && B != active) {  // uniform; otherwise no lane's sets change
-            if (bit) {
-              lt |= eq & ~B;
-              eq &= B;
-            } else {
-              eq &= ~B;
-            }
-          }
-          // after each symbol: stop once, within every group of lanes equal
-          // so far, the bits still to come agree too (the groups can no
-          // longer split, so no rank can change)
-          if (b % 5 == 0 && b > 0) {
-            const uint64_t rest = code & ((1ull << b) - 1);
-            const int leader = valid ? __builtin_ctzll(eq) : (int)lane;
-            const uint64_t lead_rest = __shfl(rest, leader, kWave);
-            if (ballot(valid && rest != lead_rest) == 0) break;
-          }
+      }
+    }
+
+    // buckets of 2..64 keys, as many at once as fit in the 64 lanes
+    uint64_t todo = ballot(sane && cnt_l >= 2 && cnt_l <= kStrWaveBucket);
+    while (todo) {
+      uint64_t batch = 0;
+      uint32_t used = 0;
+      while (todo) {  // uniform: the next buckets in cell order while they fit
+        const int j = __builtin_ctzll(todo);
+        const uint32_t cj = __builtin_amdgcn_readlane(cnt_l, j);
+        if (used + cj > (uint32_t)kWave) break;
+        batch |= 1ull << j;
+        used += cj;
+        todo &= todo - 1;
+      }
+      // bucket k of the batch takes lanes [off_k, off_k + cnt_k)
+      const bool in_batch = (batch >> lane) & 1u;
+      const uint32_t sz = in_batch ? cnt_l : 0u;
+      const uint32_t off = wave_inclusive_scan(sz) - sz;
+      const uint32_t ord = count_below(batch);
+      if (in_batch) {
+        slot_s[wv][ord] = s_l;
+        slot_off[wv][ord] = off;
+        slot_cnt[wv][ord] = cnt_l;
+      }
+      const uint32_t nb = (uint32_t)__builtin_popcountll(batch);
+      uint32_t mine = 0;  // this lane's bucket: the last whose first lane is at or below it
+      for (uint32_t k = 1; k < nb; ++k) mine += slot_off[wv][k] <= lane ? 1u : 0u;
+      const bool valid = lane < used;
+      const uint32_t boff = slot_off[wv][mine], bcnt = slot_cnt[wv][mine];
+      const uint64_t bs = slot_s[wv][mine];
+      const uint64_t active = valid ? (bcnt >= 64 ? ~0ull : ((1ull << bcnt) - 1) << boff) : 0ull;
+      Str16 k{};
+      uint32_t v = 0;
+      if (valid) {
+        k = keys[bs + (lane - boff)];
+        if constexpr (PAIRS) v = vals[bs + (lane - boff)];
+      }
+      const uint64_t code = str27_rest_code(k, desc);
+      // lanes of the own bucket equal so far (eq) and smaller (lt)
+      uint64_t eq = active, lt = 0;
+      for (int b = 59; b >= 0; --b) {
+        const uint64_t bit = (code >> b) & 1u;
+        const uint64_t B = ballot(valid && bit);
+        const uint64_t spread = 0ull - bit;
+        lt |= eq & ~B & spread;
+        eq &= ~(B ^ spread);
+        // after each symbol: stop once, within every group of lanes equal
+        // so far, the bits still to come agree too (the groups can no
+        // longer split, so no rank can change)
+        if (b % 5 == 0 && b > 0) {
+          const uint64_t rest = code & ((1ull << b) - 1);
+          const int leader = valid ? __builtin_ctzll(eq) : (int)lane;
+          const uint64_t lead_rest = __shfl(rest, leader, kWave);
+          if (ballot(valid && rest != lead_rest) == 0) break;
         }
-        const uint32_t rank = (uint32_t)__builtin_popcountll(lt) + count_below(eq);
-        if (valid) {
-          keys[s + rank] = k;
-          if constexpr (PAIRS) vals[s + rank] = v;
-        }
-      } else {
-        // a long bucket: already in order when its keys agree on the twelve
-        // symbols (the input order is the order of equal keys)
-        uint64_t lo = ~0ull, hi = 0;
-        for (uint32_t i = lane; i < cnt; i += kWave) {
-          const uint64_t code = str27_rest_code(keys[s + i], false);
-          lo = code < lo ? code : lo;
-          hi = code > hi ? code : hi;
-        }
-        for (int o = kWave / 2; o > 0; o >>= 1) {  // every lane holds at least one key
-          const uint64_t l2 = __shfl_xor(lo, o, kWave), h2 = __shfl_xor(hi, o, kWave);
-          lo = l2 < lo ? l2 : lo;
-          hi = h2 > hi ? h2 : hi;
-        }
-        if (lo != hi && lane == 0) {
-          const uint32_t at = atomicAdd(q.list_count, 1u);
-          if (at < q.list_cap) {
-            q.list[at] = s;
-            q.list[q.list_cap + at] = s + cnt;
-          }
-        }
+      }
+      const uint32_t rank = (uint32_t)__builtin_popcountll(lt) + count_below(eq);
+      if (valid) {
+        keys[bs + rank] = k;
+        if constexpr (PAIRS) vals[bs + rank] = v;
       }
     }
   }
