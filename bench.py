@@ -467,7 +467,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-arrays", type=int, default=4096)
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--served-requests", type=int, default=4000)
+    ap.add_argument("--served-requests", type=int, default=10000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB read + 1 GiB write kernel (scale reference for PMC byte counters)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS),
@@ -601,14 +601,16 @@ def main() -> int:
     if not args.no_served:
         from paper_2107_01391_amd import serve
         print("[bench] served: per-request vs batched", file=sys.stderr, flush=True)
-        # p99 is the 1%-tail of the latencies: a few thousand requests per
-        # rate keep it from resting on a handful of them
-        rows = serve.sweep([2000.0, 4000.0, 8000.0, 16000.0, 32000.0, 0.0], args.served_requests, 200, 1 << 28, 4,
-                           verbose=False)
-        served = {"trace": f"{args.served_requests} requests after 200 warm-up, sizes log-uniform [2^10, 2^22], "
+        # p99 is the 1%-tail of the latencies: 10,000 requests per rate put
+        # 100 of them past it (the 3-seed study with 20,000 per rate is in
+        # profiles/served_u32_pairs_loguniform_sweep.md)
+        rows = serve.sweep([2000.0, 2500.0, 3000.0, 4000.0, 8000.0, 16000.0, 0.0], args.served_requests, 1000,
+                           1 << 28, 4, verbose=False)
+        gate = serve.gate(rows)
+        served = {"trace": f"{args.served_requests} requests after 1000 warm-up, sizes log-uniform [2^10, 2^22], "
                            "Poisson arrivals (rate 0 = closed loop), arena 2^28 keys, 4 streams",
                   "rows": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for r in rows],
-                  "equal_p99": serve.gate(rows)}
+                  "equal_p99": gate, "crossover": serve.crossover(gate)}
 
     cpu = None
     if not args.no_cpu_baseline:
