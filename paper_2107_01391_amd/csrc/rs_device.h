@@ -268,6 +268,24 @@ __device__ __forceinline__ uint32_t look_back(const uint32_t *status, uint64_t t
   return excl;
 }
 
+// Non-temporal loads for the count kernels' reads of the keys (read once,
+// nothing reused).  Measured on MI355X: a streaming read rises from 6.2 to
+// 7.0 TB/s with the hint and the per-tile count of 2^28 u32 keys from 0.25
+// to 0.20 ms; the scatter's loads and stores are faster without it.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+  if constexpr (sizeof(T) == 16) {
+    const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    T r;
+    __builtin_memcpy(&r, &x, 16);
+    return r;
+  } else {
+    return __builtin_nontemporal_load(p);
+  }
+}
+
 __device__ __forceinline__ void lds_add(uint32_t *p, uint32_t v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }

@@ -11,7 +11,9 @@
 //                            3.2): exclusive scan of cell counts in
 //                            lexicographic order, single pass with decoupled
 //                            look-back between chunks; rs_cell_scan_reduce /
-//                            _spine / _down scan a large table in three passes.
+//                            _spine / _down scan a large table in three passes;
+//                            rs_group_scan scans one array's per-tile table in
+//                            one launch from what rs_tile_histogram leaves.
 //   rs_rank_scatter          stable emission of one dimension group: ranks
 //                            each key among the tile's keys of its cell, gets
 //                            the tile's offset per cell (from the scanned
@@ -53,7 +55,7 @@ template <typename K, int VEC>
 __device__ __forceinline__ void load_keys(const K *__restrict__ keys, bool aligned, uint64_t e, uint64_t end,
                                           K (&k)[VEC], bool (&valid)[VEC]) {
   if (aligned && e + VEC <= end) {
-    const uint4 raw = *reinterpret_cast<const uint4 *>(keys + e);
+    const uint4 raw = ld_stream(reinterpret_cast<const uint4 *>(keys + e));
     const K *kk = reinterpret_cast<const K *>(&raw);
 #pragma unroll
     for (int q = 0; q < VEC; ++q) {
@@ -64,7 +66,7 @@ __device__ __forceinline__ void load_keys(const K *__restrict__ keys, bool align
 #pragma unroll
     for (int q = 0; q < VEC; ++q) {
       valid[q] = e + q < end;
-      if (valid[q]) k[q] = keys[e + q];
+      if (valid[q]) k[q] = ld_stream(keys + e + q);
       else k[q] = K{};
     }
   }
@@ -191,6 +193,15 @@ struct TileHistParams {
   uint32_t *counts;  // flat table (see tile_span)
   const TileDesc *tiles;   // many arrays: resolved tiles
   const uint32_t *ntotal;  // many arrays: tiles in use
+  // one array (the table then feeds rs_group_scan): with several tiles per
+  // workgroup the table receives each tile's count of earlier tiles of its
+  // workgroup (per cell) and groups[d * ngroups + workgroup] the
+  // workgroup's count of cell d (groups null: one tile per workgroup, the
+  // table holds the counts); before[d * ngroups + workgroup] receives the
+  // workgroup's count of all cells below d.  ngroups = the grid.
+  uint32_t *groups;
+  uint32_t *before;
+  uint64_t ngroups;
 };
 
 // Per-tile counts of one dimension group; each workgroup takes TPW
@@ -236,7 +247,7 @@ __global__ __launch_bounds__(BLOCK) void rs_tile_histogram(const TileHistParams<
 #pragma unroll
       for (int r = 0; r < KPT; ++r) {
         const uint64_t e = sp.elem0 + (uint64_t)r * BLOCK + t;
-        k[r] = e < sp.end ? keys[e] : K{};
+        k[r] = e < sp.end ? ld_stream(keys + e) : K{};
       }
 #pragma unroll
       for (int r = 0; r < KPT; ++r) {
@@ -246,7 +257,41 @@ __global__ __launch_bounds__(BLOCK) void rs_tile_histogram(const TileHistParams<
     }
   }
   __syncthreads();
-  // TPW consecutive entries per cell when the tiles are one array's
+  if constexpr (!SEG) {
+    // per cell d: the count of each tile, or with several tiles the count
+    // of earlier tiles of this workgroup (into the table) and the
+    // workgroup's total (into groups); a cell's TPW entries sit in TPW
+    // consecutive lanes of one wave.  The workgroup's total of d replaces
+    // cnt[d] (read only by the lane of tile 0 of cell d, in the same wave,
+    // before), then the totals are scanned over the cells.
+    static_assert(kWave % TPW == 0 && BLOCK % kWave == 0, "a cell's lanes share a wave");
+    __shared__ uint32_t wsum[BLOCK / kWave];
+    for (uint32_t i0 = 0; i0 < h.cells * TPW; i0 += BLOCK) {
+      const uint32_t i = i0 + t;
+      const bool in = i < h.cells * TPW;
+      const uint32_t d = i / TPW, jj = i % TPW;
+      const uint64_t e0 = in ? s_entry0[jj] : ~0ull;
+      uint32_t c = 0;
+      if (e0 != ~0ull)
+        for (uint32_t r = 0; r < h.copies; ++r) c += cnt[jj * tstride + r * cstride + d];
+      uint32_t incl = c;
+#pragma unroll
+      for (int o = 1; o < TPW; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o, TPW);
+        if (jj >= (uint32_t)o) incl += y;
+      }
+      if (e0 != ~0ull) h.counts[e0 + (uint64_t)d * s_estride[jj]] = TPW > 1 ? incl - c : c;
+      if (in && jj == TPW - 1) {
+        if constexpr (TPW > 1) h.groups[(uint64_t)d * h.ngroups + blockIdx.x] = incl;
+        cnt[d] = incl;
+      }
+    }
+    __syncthreads();
+    block_exclusive_scan<BLOCK>(cnt, h.cells, wsum);
+    for (uint32_t d = t; d < h.cells; d += BLOCK) h.before[(uint64_t)d * h.ngroups + blockIdx.x] = cnt[d];
+    return;
+  }
+  // many arrays: each tile's counts
   for (uint32_t i = t; i < h.cells * TPW; i += BLOCK) {
     const uint32_t d = i / TPW, jj = i % TPW;
     const uint64_t e0 = s_entry0[jj];
@@ -418,6 +463,79 @@ __global__ __launch_bounds__(BLOCK) void rs_cell_scan_down(const uint32_t *in, u
     if (lo + i < count) out[lo + i] = vals[i] + base;
 }
 
+// One array's per-tile table scanned in cell-major order in one launch:
+// entry (c, t) becomes the count of every earlier cell plus the count of
+// cell c in earlier tiles.  The count kernel leaves, per cell, either every
+// tile's count (one tile per workgroup: the table rows are the units) or,
+// with several tiles per workgroup, each tile's count of earlier tiles of
+// its workgroup plus the workgroup's total in `groups` (the units); and in
+// `before` each workgroup's count of the cells below c, so that a row's
+// start is the sum of its `before` row: no workgroup waits for another.
+// With groups, each row is split into segments of BLOCK * ITEMS tiles, one
+// workgroup per segment (a segment reads only the units and its own
+// entries); without, one workgroup takes the whole row (the row is scanned
+// in place).
+struct GroupScanParams {
+  uint32_t *table;         // [cells][ntiles]
+  const uint32_t *groups;  // [cells][ngroups], or null (the table rows are the units)
+  const uint32_t *before;  // [cells][ngroups]
+  uint64_t ntiles, ngroups;
+  uint32_t shift;          // log2 of the tiles per group
+  uint32_t cells, segs;    // the grid is cells * segs; segs is 1 without groups
+};
+
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_sum(uint32_t x, uint32_t *part) {
+  x = wave_sum(x);
+  if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = x;
+  __syncthreads();
+  uint32_t tot = 0;
+#pragma unroll
+  for (int w = 0; w < BLOCK / kWave; ++w) tot += part[w];
+  __syncthreads();
+  return tot;
+}
+
+template <int BLOCK, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void rs_group_scan(const GroupScanParams q) {
+  constexpr uint32_t CH = BLOCK * ITEMS;  // tiles per segment
+  __shared__ uint32_t buf[CH];
+  __shared__ uint32_t part[BLOCK / kWave];
+  const uint32_t t = threadIdx.x;
+  const uint32_t c = blockIdx.x / q.segs, r = blockIdx.x % q.segs;
+  if (c >= q.cells) return;  // uniform
+  uint32_t *row = q.table + (uint64_t)c * q.ntiles;
+  const bool grouped = q.groups != nullptr;
+  const uint32_t *units = grouped ? q.groups + (uint64_t)c * q.ngroups : row;
+  const uint32_t *brow = q.before + (uint64_t)c * q.ngroups;
+  const uint64_t t0 = (uint64_t)r * CH;
+  const uint64_t tend = grouped && q.ntiles - t0 > CH ? t0 + CH : q.ntiles;
+  const uint64_t u_first = t0 >> q.shift;
+
+  // the row's start (every earlier cell) plus the units before the segment
+  uint32_t s = 0;
+  for (uint64_t i = t; i < q.ngroups; i += BLOCK) s += brow[i];
+  for (uint64_t i = t; i < u_first; i += BLOCK) s += units[i];
+  uint32_t carry = block_sum<BLOCK>(s, part);
+
+  // BLOCK * ITEMS tiles at a time (one step with groups): their units
+  // scanned in LDS
+  for (uint64_t c0 = t0; c0 < tend; c0 += CH) {
+    const uint32_t tn = tend - c0 < CH ? (uint32_t)(tend - c0) : CH;
+    const uint64_t u0 = c0 >> q.shift;
+    const uint32_t un = (uint32_t)(((c0 + tn - 1) >> q.shift) - u0 + 1);
+    for (uint32_t i = t; i < un; i += BLOCK) buf[i] = units[u0 + i];
+    __syncthreads();
+    const uint32_t tot = block_exclusive_scan<BLOCK>(buf, un, part);
+    for (uint32_t i = t; i < tn; i += BLOCK) {
+      const uint64_t tile = c0 + i;
+      row[tile] = carry + (grouped ? buf[(tile >> q.shift) - u0] + row[tile] : buf[i]);
+    }
+    carry += tot;
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------- tile ranking helpers
 
 // Ranks this thread's KPT keys among the keys of the same cell in its wave.
@@ -565,14 +683,15 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
   // ---- prescanned: this tile's output offset of each cell, relative to
   // its array, loaded together with the keys so that the tile waits for
   // memory once
-  uint32_t rel[CPT];
+  // (the array's base is subtracted only where the offsets are used, so
+  // that no wait for it comes before the key loads are issued)
+  uint32_t rel[CPT], rel0 = 0;
   if constexpr (MODE != kChained) {
-    const uint32_t rel0 = MODE == kPrescannedSeg ? p.tile_offsets[sp.block] : 0u;
+    if constexpr (MODE == kPrescannedSeg) rel0 = p.tile_offsets[sp.block];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
       const uint32_t d = t + c * BLOCK;
-      // wraps consistently in 32 bits: the difference is below 2^30
-      rel[c] = d < p.bins ? p.tile_offsets[sp.entry0 + (uint64_t)d * sp.estride] - rel0 : 0u;
+      rel[c] = d < p.bins ? p.tile_offsets[sp.entry0 + (uint64_t)d * sp.estride] : 0u;
     }
   }
 
@@ -638,7 +757,9 @@ __global__ __launch_bounds__(BLOCK) void rs_rank_scatter(const PassParams<Digit>
         }
         gdelta[d] = p.digit_start[d] + excl - tstart[d];
       } else {
-        gdelta[d] = rel[c] - tstart[d];
+        // wraps consistently in 32 bits: the offset relative to the array
+        // is below 2^30
+        gdelta[d] = rel[c] - rel0 - tstart[d];
       }
     }
   }

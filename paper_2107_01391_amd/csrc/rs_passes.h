@@ -1,7 +1,10 @@
 // rs_passes.h -- launch sequence of one prescanned pass (reduce-then-scan):
 //
 //   rs_tile_histogram   per-tile counts of the pass's cells, flat table
-//   rs_cell_scan_*      one exclusive scan of the whole table
+//   (scan)              one exclusive scan of the whole table: for one
+//                       array rs_group_scan (one launch; the count kernel
+//                       has already summed each workgroup's tiles), for
+//                       many arrays rs_cell_scan_reduce/_spine/_down
 //   rs_rank_scatter     stable scatter with offsets read from the table
 //
 // No tile waits on another: on MI355X every serialised global round trip
@@ -23,6 +26,10 @@ constexpr uint32_t kTileHistBudget = 24 * 1024;
 
 // Keys are read as KI and written as KO (narrowed on a first pass, widened
 // on a last one; see rs_rank_scatter).
+// For one array (SEG false), `sums` is the region the plan sizes with
+// group_words: the workgroup totals of the count kernel (with several tiles
+// per workgroup), then each workgroup's counts of the cells below each
+// cell; for many arrays it holds the chunk sums of the three-launch scan.
 template <typename K, class Digit, int BITS, int BLOCK, bool SEG, typename KI = K, typename KO = K>
 rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const KI *src, KO *dst,
                           const uint32_t *srcv, uint32_t *dstv, uint64_t n, uint64_t ntiles_bound,
@@ -33,8 +40,17 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
   rs_status st;
   const uint64_t count = (uint64_t)cells * ntiles_bound;
   const uint32_t nchunks = (uint32_t)((count + kBigScanChunk - 1) / kBigScanChunk);
+  const uint32_t tpw = tile_hist_tpw(cells, ntiles_bound);
+  // one array: rows of workgroup totals (several tiles per workgroup) or of
+  // the table itself (one tile per workgroup), and the workgroups' counts
+  // below each cell, for rs_group_scan
+  const uint64_t ngroups = (ntiles_bound + tpw - 1) / tpw;
+  const uint64_t rows_words = (uint64_t)cells * ngroups;
+  uint32_t *groups = tpw > 1 ? sums : nullptr;
+  uint32_t *below = tpw > 1 ? sums + (rows_words + 63) / 64 * 64 : sums;
 
   TileHistParams<Digit> th;
+  memset(&th, 0, sizeof th);
   th.digit = digit;
   th.cells = cells;
   th.ntiles = (uint32_t)ntiles_bound;
@@ -42,6 +58,11 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
   th.counts = table;
   th.tiles = tiles;
   th.ntotal = ntotal;
+  if constexpr (!SEG) {
+    th.groups = groups;
+    th.before = below;
+    th.ngroups = ngroups;
+  }
   auto histogram = [&]<int TPW>() {
     th.copies = count_copies(cells * TPW, kTileHistBudget);
     const size_t lds = (size_t)TPW * th.copies * (cells + 1) * 4;
@@ -49,30 +70,39 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
              hipLaunchKernelGGL((rs_tile_histogram<KI, Digit, 256, TPW, TILE, SEG>),
                                 dim3((uint32_t)((ntiles_bound + TPW - 1) / TPW)), dim3(256), lds, stream, th, src));
   };
-  // several tiles per workgroup once there are enough tiles to fill every
-  // CU with them: each workgroup then writes runs of TPW entries of the
-  // cell-major table instead of single words (32 tiles of 256 cells make
-  // 128-byte runs with one table copy per tile in LDS; wider tables keep 8
-  // tiles, so that at least four workgroups per CU stay in flight); one
-  // tile each below that
-  const uint64_t many = (uint64_t)cu_count() * 32;
-  if (cells <= 256 && ntiles_bound >= 2 * many) histogram.template operator()<32>();
-  else if (ntiles_bound >= many) histogram.template operator()<8>();
+  if (tpw == 32) histogram.template operator()<32>();
+  else if (tpw == 8) histogram.template operator()<8>();
   else histogram.template operator()<1>();
   if ((st = check_launch("rs_tile_histogram")) != RS_OK) return st;
 
-  const uint32_t *cdev = SEG ? ntotal : nullptr;
-  RowMaps nomaps;
-  memset(&nomaps, 0, sizeof nomaps);
-  RS_TIMED("rs_cell_scan", stream,
-           hipLaunchKernelGGL((rs_cell_scan_reduce<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
-                              stream, table, count, cdev, cells, sums, nomaps));
-  RS_TIMED("rs_cell_scan", stream,
-           hipLaunchKernelGGL((rs_cell_scan_spine<1024, kBigScanChunk>), dim3(1), dim3(1024), 0, stream, sums, count,
-                              cdev, cells));
-  RS_TIMED("rs_cell_scan", stream,
-           hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
-                              stream, table, count, cdev, cells, sums, table, nomaps));
+  if constexpr (SEG) {
+    const uint32_t *cdev = ntotal;
+    RowMaps nomaps;
+    memset(&nomaps, 0, sizeof nomaps);
+    RS_TIMED("rs_cell_scan", stream,
+             hipLaunchKernelGGL((rs_cell_scan_reduce<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
+                                stream, table, count, cdev, cells, sums, nomaps));
+    RS_TIMED("rs_cell_scan", stream,
+             hipLaunchKernelGGL((rs_cell_scan_spine<1024, kBigScanChunk>), dim3(1), dim3(1024), 0, stream, sums,
+                                count, cdev, cells));
+    RS_TIMED("rs_cell_scan", stream,
+             hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
+                                stream, table, count, cdev, cells, sums, table, nomaps));
+  } else {
+    constexpr uint32_t kSegTiles = kScanBlock * 16;
+    GroupScanParams gs;
+    gs.table = table;
+    gs.groups = groups;
+    gs.before = below;
+    gs.ntiles = ntiles_bound;
+    gs.ngroups = ngroups;
+    gs.shift = (uint32_t)__builtin_ctz(tpw);
+    gs.cells = cells;
+    gs.segs = groups ? (uint32_t)((ntiles_bound + kSegTiles - 1) / kSegTiles) : 1u;
+    RS_TIMED("rs_cell_scan", stream,
+             hipLaunchKernelGGL((rs_group_scan<kScanBlock, 16>), dim3(cells * gs.segs), dim3(kScanBlock), 0, stream,
+                                gs));
+  }
   if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
 
   PassParams<Digit> pp;

@@ -1,5 +1,6 @@
 // rs_plan.cpp -- host planner (no device code).
 #include "rs_plan.h"
+#include "rs_internal.h"
 
 #include <string.h>
 
@@ -311,7 +312,12 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
     const uint64_t entries = (uint64_t)p.bins * p.ntiles;
     p.scan_chunks = (uint32_t)((entries + kBigScanChunk - 1) / kBigScanChunk);
     p.off_table = take(entries * 4);
-    p.off_sums = take((size_t)p.scan_chunks * 4);
+    uint64_t gw = 0;
+    for (uint32_t i = 0; i < p.npasses; ++i) {
+      const uint64_t w = group_words(p.pass_cells[i], p.ntiles);
+      gw = w > gw ? w : gw;
+    }
+    p.off_sums = take((size_t)(gw > p.scan_chunks ? gw : p.scan_chunks) * 4);
     if (p.mode == kModeStr16 && k.base == 27 && k.ndims == 16 && p.npasses == 8 && n >= kStrBucketMinN) {
       // 27^4 buckets of the four leading symbols; at most n / 65 of them
       // hold more than 64 keys (the ones a wave cannot sort)
@@ -342,6 +348,25 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
   }
   p.total = off ? off : 256;
   return RS_OK;
+}
+
+// Several tiles per workgroup once there are enough tiles to fill every CU
+// with them: each workgroup then writes runs of TPW entries of the
+// cell-major table instead of single words (32 tiles of 256 cells make
+// 128-byte runs with one table copy per tile in LDS; wider tables keep 8
+// tiles, so that at least four workgroups per CU stay in flight); one tile
+// each below that.
+uint32_t tile_hist_tpw(uint32_t cells, uint64_t ntiles) {
+  const uint64_t many = (uint64_t)cu_count() * 32;
+  if (cells <= 256 && ntiles >= 2 * many) return 32;
+  if (ntiles >= many) return 8;
+  return 1;
+}
+
+uint64_t group_words(uint32_t cells, uint64_t ntiles) {
+  const uint32_t tpw = tile_hist_tpw(cells, ntiles);
+  const uint64_t rows = ((uint64_t)cells * ((ntiles + tpw - 1) / tpw) + 63) / 64 * 64;
+  return tpw > 1 ? 2 * rows : rows;
 }
 
 uint32_t prescan_block(const Tuning &tune, uint32_t key_bytes, uint32_t bits) {

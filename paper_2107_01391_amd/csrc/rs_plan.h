@@ -98,7 +98,9 @@ struct Plan {
   size_t off_ctrl = 0, ctrl_bytes = 0, status_bytes = 0;
   size_t off_counts = 0, off_starts = 0;
   size_t off_map_lo = 0, off_map_hi = 0;  // literal: traverse maps (complemented minima, maxima)
-  size_t off_table = 0, off_sums = 0;  // prescanned: per-tile counts, chunk sums
+  // prescanned: per-tile counts, and at off_sums what the count kernel
+  // leaves for the scan (group_words)
+  size_t off_table = 0, off_sums = 0;
   uint32_t scan_chunks = 0;            // chunks of the cell scan
   SegLayout seg;                       // batched form
   // base-27 16-symbol strings, prescanned: the passes over the four leading
@@ -120,6 +122,13 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
 // Threads per tile of prescanned passes for keys of `key_bytes` and passes
 // of kernel variant `bits` (the choice with_block() makes on the device side).
 uint32_t prescan_block(const Tuning &tune, uint32_t key_bytes, uint32_t bits);
+// Tiles per workgroup of the per-tile count kernel for `cells` cells over
+// `ntiles` tiles (1, 8 or 32; from the device's CU count).
+uint32_t tile_hist_tpw(uint32_t cells, uint64_t ntiles);
+// Words the count kernel of one pass leaves for the scan of one array's
+// table: per cell and workgroup its counts of the cells below, and with
+// several tiles per workgroup also its total.
+uint64_t group_words(uint32_t cells, uint64_t ntiles);
 // Layout of the segmented form for passes [0, npasses) of `p`.
 rs_status make_seg_layout(const Plan &p, uint32_t npasses, uint64_t total, uint64_t extent, uint32_t nseg,
                           bool own_alt, uint32_t block, SegLayout *L, std::string *why);

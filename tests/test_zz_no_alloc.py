@@ -62,8 +62,8 @@ def test_noalloc_equals_caller_scratch_u32(sizes):
 
 def test_noalloc_strings_then_smaller_fixed_point():
     d = B.key_desc("str", base=27, ndims=16)
-    w = workloads.strings16(2_400_000, seed_extra=(5,))
-    _say("noalloc strings n=2400000")
+    w = workloads.strings16(2_300_000, seed_extra=(5,))
+    _say("noalloc strings n=2300000")
     got, ref = _both(d, w.keys, w.vals, np.uint8, (w.n, 16))
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
     d = B.key_desc("fixed_i64", base=10, ndims=9, frac_digits=3)
