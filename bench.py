@@ -473,6 +473,7 @@ def main() -> int:
     ap.add_argument("--workload", choices=sorted(WORKLOADS),
                     help="time only this workload (default tuning) and print its line")
     ap.add_argument("--no-workloads", action="store_true", help="skip the other full-size workloads")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph replay of the sort")
     ap.add_argument("--cpu-full", action="store_true",
                     help="time the CPU oracle on the full 2^28-pair input (minutes) and record it under profiles/")
     ap.add_argument("--pmc-summary", metavar="WORKLOAD",
@@ -583,6 +584,29 @@ def main() -> int:
     digest_ok = oracle_digest_match(keys_out, vals_out, n)
     print(f"[bench] oracle digest {'match' if digest_ok else ('MISMATCH' if digest_ok is False else 'not stored')}",
           file=sys.stderr, flush=True)
+
+    # the same sort captured once as a HIP graph (rs_graph_sort) and replayed
+    # the same number of steps: the same kernels on the same data, fewer
+    # gaps between dependent launches; reported beside the plain call
+    graph = None
+    if not args.no_graph:
+        keys_out.zero_()
+        vals_out.zero_()
+        g = B.rs_graph_sort(desc, keys, keys_out, vals, vals_out, n, tmp, tmp.numel())
+        for _ in range(args.warmup):
+            g.launch(stream)
+        torch.cuda.synchronize()
+        g_ok = oracle_digest_match(keys_out, vals_out, n)
+        ga, gb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ga.record(stream)
+        for _ in range(args.steps):
+            g.launch(stream)
+        gb.record(stream)
+        torch.cuda.synchronize()
+        g_ms = ga.elapsed_time(gb) / args.steps
+        g.close()
+        graph = {"ms_per_step": round(g_ms, 4), "gkeys_per_s": round(n / (g_ms / 1e3) / 1e9, 3),
+                 "oracle_digest_match": g_ok}
     del keys_out, vals_out, tmp
     torch.cuda.empty_cache()
 
@@ -625,7 +649,7 @@ def main() -> int:
         "config": {"workload": f"uniform_u32_pairs: {n} uint32 keys uniform over [0, 2^32), uint32 index payload, "
                                "base 256, 4 dimensions, stable ascending (rs_sort_pairs)",
                    "n": n, "passes": passes},
-        "roofline": roofline, "whole_sort": whole, "cpu_baseline": cpu, "workloads": others,
+        "roofline": roofline, "whole_sort": whole, "graph_replay": graph, "cpu_baseline": cpu, "workloads": others,
         "batched_vs_per_array": batched,
         "served": served, "output_check": ok, "oracle_digest_match": digest_ok,
         "device": torch.cuda.get_device_name(0),

@@ -268,10 +268,11 @@ __device__ __forceinline__ uint32_t look_back(const uint32_t *status, uint64_t t
   return excl;
 }
 
-// Non-temporal loads for the count kernels' reads of the keys (read once,
-// nothing reused).  Measured on MI355X: a streaming read rises from 6.2 to
-// 7.0 TB/s with the hint and the per-tile count of 2^28 u32 keys from 0.25
-// to 0.20 ms; the scatter's loads and stores are faster without it.
+// Non-temporal loads for the count kernels' 16-byte reads of the keys
+// (read once, nothing reused).  Measured on MI355X: a streaming read rises
+// from 6.2 to 7.0 TB/s with the hint and the per-tile count of 2^28 u32
+// keys from 0.25 to 0.20 ms; the scatter's loads and stores, and the
+// batched form's one-key-per-lane count loads, are faster without it.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(BLOCK) void rs_tile_histogram(const TileHistParams<
 #pragma unroll
       for (int r = 0; r < KPT; ++r) {
         const uint64_t e = sp.elem0 + (uint64_t)r * BLOCK + t;
-        k[r] = e < sp.end ? ld_stream(keys + e) : K{};
+        k[r] = e < sp.end ? keys[e] : K{};  // (non-temporal 4-byte loads measured slower here)
       }
 #pragma unroll
       for (int r = 0; r < KPT; ++r) {
