@@ -70,9 +70,13 @@ rs_status prescanned_pass(const Digit &digit, uint32_t cells, bool pairs, const 
              hipLaunchKernelGGL((rs_tile_histogram<KI, Digit, 256, TPW, TILE, SEG>),
                                 dim3((uint32_t)((ntiles_bound + TPW - 1) / TPW)), dim3(256), lds, stream, th, src));
   };
-  if (tpw == 32) histogram.template operator()<32>();
-  else if (tpw == 8) histogram.template operator()<8>();
-  else histogram.template operator()<1>();
+  switch (tpw) {
+  case 32: histogram.template operator()<32>(); break;
+  case 8: histogram.template operator()<8>(); break;
+  case 4: histogram.template operator()<4>(); break;
+  case 2: histogram.template operator()<2>(); break;
+  default: histogram.template operator()<1>(); break;
+  }
   if ((st = check_launch("rs_tile_histogram")) != RS_OK) return st;
 
   if constexpr (SEG) {

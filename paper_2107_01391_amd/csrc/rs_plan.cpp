@@ -350,17 +350,27 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
   return RS_OK;
 }
 
-// Several tiles per workgroup once there are enough tiles to fill every CU
-// with them: each workgroup then writes runs of TPW entries of the
-// cell-major table instead of single words (32 tiles of 256 cells make
-// 128-byte runs with one table copy per tile in LDS; wider tables keep 8
-// tiles, so that at least four workgroups per CU stay in flight); one tile
-// each below that.
+// Tiles per count workgroup.  Each workgroup writes runs of TPW entries of
+// the cell-major table (32 tiles of 256 cells: 128-byte runs); with `many`
+// = 32 tiles per CU:
+// - at most 256 cells: 32 from 2 * many tiles, 8 from many;
+// - below that, 256 cells: the power of two nearest (on a log scale) to the
+//   tiles that make two workgroups per CU, at most 8 (measured in the sort
+//   on MI355X: 2^24 u32 pairs 408 -> 396 us with 4, 2^25 720 -> 670 us
+//   with 8, against one tile each); fewer cells keep one tile each, since
+//   more tiles per workgroup leave fewer LDS copies of each table and lanes
+//   of a wave collide on fewer words (100 cells at 12,208 tiles: 0.153 ms
+//   per pass with 32 tiles and one copy, 0.099 ms with 8 and four copies);
+// - more cells: 8 from many tiles (LDS), else 1.
 uint32_t tile_hist_tpw(uint32_t cells, uint64_t ntiles) {
-  const uint64_t many = (uint64_t)cu_count() * 32;
+  const uint64_t cus = (uint64_t)cu_count(), many = cus * 32;
   if (cells <= 256 && ntiles >= 2 * many) return 32;
   if (ntiles >= many) return 8;
-  return 1;
+  if (cells != 256) return 1;
+  const double per = (double)ntiles / (2.0 * (double)cus);
+  uint32_t tpw = 1;
+  while (tpw < 8 && (double)tpw * 1.4142135623730951 < per) tpw <<= 1;
+  return tpw;
 }
 
 uint64_t group_words(uint32_t cells, uint64_t ntiles) {

@@ -1,5 +1,5 @@
 """Sizes at the edges of the one-launch table scan of single arrays: the
-count kernel's groups of 8 or 32 tiles with a short last group, and table
+count kernel's groups of 2, 4, 8 or 32 tiles with a short last group, and table
 rows split into several 4096-tile segments with a short last segment.
 
 At these sizes the output is checked by the properties that define a
@@ -47,6 +47,8 @@ def _check_stable_sort(torch, keys_in, keys_out, vals_out, n):
 
 @pytest.mark.parametrize("n,base,ndims,what", [
     ((1 << 21) + 1, 256, 4, "one tile per count workgroup, one segment per row"),
+    (1024 * TILE + 1, 256, 4, "2 tiles per count workgroup, last group of 1 tile"),
+    (2048 * TILE + 1, 256, 4, "4 tiles per count workgroup, last group of 1 tile"),
     (8192 * TILE + 1, 256, 4, "8 tiles per count workgroup, last group of 1 tile, 3 segments"),
     (16388 * TILE - 5, 256, 4, "32 tiles per count workgroup, last group of 4 tiles, last segment of 4 tiles"),
     (9000 * TILE + 77, 10, 9, "100-cell passes (base 10), 8 tiles per count workgroup, short last group"),
