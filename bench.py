@@ -32,7 +32,8 @@ METRIC = "Gkeys/s + % HBM peak, 256M u32 KV sort; batched vs per-array at p99 la
 HBM_PEAK_GBS = 8000.0
 FULL_N = 1 << 28
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2107_01391_amd", "csrc", f)
-                  for f in ("rs_kernels.h", "rs_device.h", "rs_passes.h", "rs_sort.hip", "rs_seg_kernels.h")]
+                  for f in ("rs_kernels.h", "rs_device.h", "rs_passes.h", "rs_sort.hip", "rs_seg_kernels.h",
+                            "rs_str_buckets.h", "rs_segmented.h", "rs_plan.cpp")]
 # The other full-size workloads: keys-only decimals over the literal 10^6-cell
 # space, fixed-point decimals, and 16-byte strings; algorithmic bytes per key
 # are the method's minimum (hash read of the key; scatter read and write of
