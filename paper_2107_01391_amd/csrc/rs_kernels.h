@@ -215,7 +215,33 @@ __global__ __launch_bounds__(BLOCK) void rs_tile_histogram(const TileHistParams<
   for (uint32_t i = t; i < TPW * tstride; i += BLOCK) cnt[i] = 0;
   __syncthreads();
   const uint64_t t0 = (uint64_t)blockIdx.x * TPW;
-  for (uint32_t jj = 0; jj < (uint32_t)TPW; ++jj) {
+  bool whole = false;
+  if constexpr (!SEG && sizeof(K) >= 16) {
+    // 16-byte keys of one array, every tile of this workgroup whole and the
+    // keys aligned (uniform): one flat loop of batches without bounds tests
+    // (measured on 2^24 strings: 0.068 against 0.080 ms per pass; no gain
+    // for 4- and 8-byte keys, which keep the loop below)
+    constexpr int UNROLL = TILE / BLOCK < 4 ? TILE / BLOCK : 4;
+    constexpr uint32_t BATCH = BLOCK * UNROLL;
+    static_assert(TILE % BATCH == 0, "whole batches per tile");
+    whole = ((uintptr_t)keys % 16) == 0 && (t0 + TPW) * TILE <= h.n;
+    if (whole) {
+      if (t < (uint32_t)TPW) {
+        s_entry0[t] = t0 + t;
+        s_estride[t] = h.ntiles;
+      }
+      const K *wk = keys + t0 * TILE;
+      for (uint32_t b = 0; b < (uint32_t)(TPW * TILE / BATCH); ++b) {
+        uint32_t *row = cnt + (b / (TILE / BATCH)) * tstride;
+        K k[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) k[u] = ld_stream(wk + (uint64_t)b * BATCH + u * BLOCK + t);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) lds_count(row, cstride, h.copies, h.digit(k[u]), true);
+      }
+    }
+  }
+  for (uint32_t jj = 0; jj < (uint32_t)TPW && !whole; ++jj) {
     const TileSpan sp = tile_span<TILE, SEG>(t0 + jj, h.n, h.ntiles, h.cells, h.tiles, h.ntotal);
     if (t == 0) {
       s_entry0[jj] = sp.valid ? sp.entry0 : ~0ull;
