@@ -471,7 +471,7 @@ __global__ __launch_bounds__(BLOCK) void rs_cell_scan_spine(uint32_t *__restrict
   }
 }
 
-template <int BLOCK, int ITEMS>
+template <int BLOCK, int ITEMS, bool SPINE = false>
 __global__ __launch_bounds__(BLOCK) void rs_cell_scan_down(const uint32_t *in, uint64_t count_host,
                                                            const uint32_t *count_dev, uint32_t count_mul,
                                                            const uint32_t *__restrict__ sums, uint32_t *out,
@@ -484,10 +484,24 @@ __global__ __launch_bounds__(BLOCK) void rs_cell_scan_down(const uint32_t *in, u
   if (lo >= count) return;  // uniform
   // literal form: no start is needed where nothing is emitted
   if (!chunk_occupied<BLOCK>(m, lo, lo + CH < count ? lo + CH : count)) return;
+  // SPINE: the chunk sums are the reduce's, unscanned; each workgroup adds
+  // up those before its chunk itself (few chunks: a small table, the
+  // literal space or the string buckets), which saves the spine launch
+  uint32_t spine = 0;
+  if constexpr (SPINE) {
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += BLOCK) spine += sums[i];
+    spine = wave_sum(spine);
+    if (threadIdx.x % kWave == 0) wsum[threadIdx.x / kWave] = spine;
+    __syncthreads();
+    spine = 0;
+#pragma unroll
+    for (int w = 0; w < BLOCK / kWave; ++w) spine += wsum[w];
+    __syncthreads();
+  }
   for (uint32_t i = threadIdx.x; i < CH; i += BLOCK) vals[i] = lo + i < count ? in[lo + i] : 0u;
   __syncthreads();
   block_exclusive_scan<BLOCK>(vals, CH, wsum);
-  const uint32_t base = sums[blockIdx.x];
+  const uint32_t base = SPINE ? spine : sums[blockIdx.x];
   for (uint32_t i = threadIdx.x; i < CH; i += BLOCK)
     if (lo + i < count) out[lo + i] = vals[i] + base;
 }

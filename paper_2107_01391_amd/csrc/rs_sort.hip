@@ -9,7 +9,8 @@
 //                              ping-ponging between the output and scratch
 // prescanned passes (large arrays), per pass (rs_passes.h):
 //   1. rs_tile_histogram       per-tile counts of the pass's group
-//   2. rs_cell_scan_reduce/_spine/_down   one exclusive scan of that table,
+//   2. rs_group_scan           one exclusive scan of that table (one launch;
+//                              many arrays: rs_cell_scan_reduce/_spine/_down),
 //                              cell-major: every tile's output offset per cell
 //   3. rs_rank_scatter         stable scatter, offsets read from the table
 // rs_sort_keys on a small space (literal):
@@ -235,10 +236,7 @@ static rs_status run_str_buckets(const Plan &pl, const void *keys_in, void *keys
            hipLaunchKernelGGL((rs_cell_scan_reduce<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
                               stream, q.counts, cells, nullptr, 1, bsums, nomaps));
   RS_TIMED("rs_cell_scan", stream,
-           hipLaunchKernelGGL((rs_cell_scan_spine<1024, kBigScanChunk>), dim3(1), dim3(1024), 0, stream, bsums,
-                              cells, nullptr, 1));
-  RS_TIMED("rs_cell_scan", stream,
-           hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems>), dim3(nchunks), dim3(kScanBlock), 0,
+           hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems, true>), dim3(nchunks), dim3(kScanBlock), 0,
                               stream, q.counts, cells, nullptr, 1, bsums, (uint32_t *)q.starts, nomaps));
   if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
 
@@ -356,17 +354,16 @@ static rs_status run_literal(const Plan &pl, const void *keys_in, void *keys_out
     RS_TIMED("rs_cell_count", stream, hipLaunchKernelGGL((rs_cell_count<uint64_t, 256>), dim3((uint32_t)blocks), dim3(256), map_lds, stream,
                        (const uint64_t *)keys_in, pl.n, pl.literal_cells, counts, maps));
   if ((st = check_launch("rs_cell_count")) != RS_OK) return st;
-  // reduce-then-scan over the cells; chunks that no row's occupied range
-  // reaches are neither read nor written
+  // reduce-then-scan over the cells (each down-sweep workgroup adds up the
+  // chunk sums before its own, no spine launch); chunks that no row's
+  // occupied range reaches are neither read nor written
   const uint64_t cells = pl.literal_cells;
   RS_TIMED("rs_cell_scan", stream,
            hipLaunchKernelGGL((rs_cell_scan_reduce<kScanBlock, kBigScanItems>), dim3(pl.scan_chunks), dim3(kScanBlock),
                               0, stream, counts, cells, nullptr, 1, sums, maps));
   RS_TIMED("rs_cell_scan", stream,
-           hipLaunchKernelGGL((rs_cell_scan_spine<1024, kBigScanChunk>), dim3(1), dim3(1024), 0, stream, sums, cells,
-                              nullptr, 1));
-  RS_TIMED("rs_cell_scan", stream,
-           hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems>), dim3(pl.scan_chunks), dim3(kScanBlock), 0,
+           hipLaunchKernelGGL((rs_cell_scan_down<kScanBlock, kBigScanItems, true>), dim3(pl.scan_chunks),
+                              dim3(kScanBlock), 0,
                               stream, counts, cells, nullptr, 1, sums, starts, maps));
   if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
   const uint32_t eb = (pl.literal_cells + 255) / 256;
