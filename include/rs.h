@@ -153,7 +153,7 @@ rs_status rs_sort_pairs(const rs_key_desc *desc, const void *keys_in, void *keys
  *   Limit: a sort whose rs_temp_bytes(desc, n, 1) exceeds
  *   RS_NOALLOC_SCRATCH_BYTES returns RS_ERR_UNSUPPORTED and launches nothing
  *   (with the default tuning: u32 pairs up to 8,134,272 keys, u64 pairs up
- *   to 5,478,208, 16-byte strings up to 2,380,224).
+ *   to 5,478,208, 16-byte strings up to 2,360,192).
  *   Every call on a device shares that device's array: calls that overlap in
  *   time on one device (other streams or threads, no ordering between them)
  *   race and give unspecified results.  Calls ordered on one stream are safe;

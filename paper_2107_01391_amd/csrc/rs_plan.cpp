@@ -325,6 +325,7 @@ rs_status make_plan(const rs_key_desc *desc, uint64_t n, bool pairs, const Tunin
       p.str_buckets = true;
       p.off_bcounts = take(cells * 4);
       p.off_bctrl = take(4);
+      p.off_bmixed = take(cells);
       p.bfill_bytes = off - p.off_bcounts;
       p.off_bstarts = take(cells * 4);
       p.off_bsums = take((cells + kBigScanChunk - 1) / kBigScanChunk * 4);

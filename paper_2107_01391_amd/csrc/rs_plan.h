@@ -109,8 +109,9 @@ struct Plan {
   // batched passes over the other twelve symbols (layout bseg, sized for
   // blist_cap buckets, at off_bseg; it reuses the alternate arrays)
   bool str_buckets = false;
-  size_t off_bcounts = 0, off_bctrl = 0, off_bstarts = 0, off_bsums = 0, off_blist = 0, off_bseg = 0;
-  size_t bfill_bytes = 0;              // counts and control words, cleared together
+  size_t off_bcounts = 0, off_bctrl = 0, off_bmixed = 0, off_bstarts = 0, off_bsums = 0, off_blist = 0,
+         off_bseg = 0;
+  size_t bfill_bytes = 0;              // counts, control word and mixed marks, cleared together
   uint32_t blist_cap = 0;
   SegLayout bseg;
   size_t total = 0;

@@ -188,6 +188,22 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
 // the device; the list's length is read back (the one synchronisation of
 // this form) and they go through the batched passes over the twelve
 // symbols.
+// Workgroups of 256 threads of a kernel that run at once on the whole chip.
+template <auto KERNEL>
+static uint32_t resident_grid() {
+  static uint32_t grid = 0;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, KERNEL, 256, 0) != hipSuccess || per_cu <= 0) {
+      (void)hipGetLastError();  // the query's error is not a launch's
+      per_cu = 4;
+    }
+    grid = (uint32_t)per_cu * (uint32_t)cu_count();
+  });
+  return grid;
+}
+
 static rs_status run_str_buckets(const Plan &pl, const void *keys_in, void *keys_out, const uint32_t *vals_in,
                                  uint32_t *vals_out, void *tmp, hipStream_t stream) {
   char *base = (char *)tmp;
@@ -216,16 +232,18 @@ static rs_status run_str_buckets(const Plan &pl, const void *keys_in, void *keys
   q.lead.ca = pl.key.descending ? kStrBucketCells : 0u;
   q.n = pl.n;
   q.counts = (uint32_t *)(base + pl.off_bcounts);
+  q.mixed = (uint8_t *)(base + pl.off_bmixed);
   q.starts = (uint32_t *)(base + pl.off_bstarts);
   q.list = (uint64_t *)(base + pl.off_blist);
   q.list_count = (uint32_t *)(base + pl.off_bctrl);
   q.list_cap = pl.blist_cap;
   q.descending = pl.key.descending ? 1u : 0u;
   if ((st = launch_fill(q.counts, pl.bfill_bytes, 0, stream)) != RS_OK) return st;
-  uint64_t grid = (pl.n + 255) / 256;
-  if (grid > (uint64_t)cu_count() * 16) grid = (uint64_t)cu_count() * 16;
+  // one contiguous range of the array per wave, as many waves as the chip
+  // holds at once
   RS_TIMED("rs_str_bucket_count", stream,
-           hipLaunchKernelGGL((rs_str_bucket_count<256>), dim3((uint32_t)grid), dim3(256), 0, stream, q, X));
+           hipLaunchKernelGGL((rs_str_bucket_count<256>), dim3(resident_grid<rs_str_bucket_count<256>>()), dim3(256),
+                              0, stream, q, X));
   if ((st = check_launch("rs_str_bucket_count")) != RS_OK) return st;
   const uint64_t cells = kStrBucketCells;
   const uint32_t nchunks = (uint32_t)((cells + kBigScanChunk - 1) / kBigScanChunk);
@@ -240,14 +258,16 @@ static rs_status run_str_buckets(const Plan &pl, const void *keys_in, void *keys
                               stream, q.counts, cells, nullptr, 1, bsums, (uint32_t *)q.starts, nomaps));
   if ((st = check_launch("rs_cell_scan")) != RS_OK) return st;
 
-  // every bucket, one wave each
-  const uint32_t sgrid = (uint32_t)cu_count() * 8;
+  // the mixed buckets: as many waves as the chip holds at once, each over
+  // an equal run of cells
   if (pairs)
     RS_TIMED("rs_str_bucket_sort", stream,
-             hipLaunchKernelGGL((rs_str_bucket_sort<256, true>), dim3(sgrid), dim3(256), 0, stream, q, X, vals_out));
+             hipLaunchKernelGGL((rs_str_bucket_sort<256, true>), dim3(resident_grid<rs_str_bucket_sort<256, true>>()), dim3(256), 0, stream,
+                                q, X, vals_out));
   else
     RS_TIMED("rs_str_bucket_sort", stream,
-             hipLaunchKernelGGL((rs_str_bucket_sort<256, false>), dim3(sgrid), dim3(256), 0, stream, q, X, nullptr));
+             hipLaunchKernelGGL((rs_str_bucket_sort<256, false>), dim3(resident_grid<rs_str_bucket_sort<256, false>>()), dim3(256), 0,
+                                stream, q, X, nullptr));
   if ((st = check_launch("rs_str_bucket_sort")) != RS_OK) return st;
 
   uint32_t nlong = 0;
