@@ -75,13 +75,42 @@ def _strings(case, n=N):
         k[:, :4] = pref[rows]
         k[:, 4:] = letters((n, 12))
         rng.shuffle(k)
+    elif case == "change_points":
+        # buckets of 2..300 keys, each one tail repeated and then another
+        # from a change point on, so that a bucket's only differing
+        # neighbours sit at the change point; in the ordered array the
+        # change points fall where a wave's 64-key step or its range of the
+        # count begins (n is 384 × 8192: ranges of 384 keys when 8192 waves
+        # count), which the count kernel sees through the key carried from
+        # the step or range before
+        sizes = rng.integers(2, 301, n // 2)
+        sizes = sizes[: np.searchsorted(np.cumsum(sizes), n) + 1]
+        sizes[-1] -= int(sizes.sum()) - n
+        nb = sizes.shape[0]
+        cells = np.sort(rng.choice(26 ** 4, nb, replace=False))
+        pref = np.stack([cells // 26 ** (3 - j) % 26 for j in range(4)], axis=1).astype(np.uint8) + np.uint8(97)
+        starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+        step = np.where(np.arange(nb) % 3 == 0, 384, 64)
+        at = (starts // step + 1) * step  # first such boundary after the bucket's start
+        inside = at < starts + sizes
+        change = np.where(inside, at - starts, rng.integers(1, np.maximum(sizes, 2)))
+        change = np.minimum(change, sizes - 1)
+        tails = letters((nb, 2, 12))
+        rows = np.repeat(np.arange(nb), sizes)
+        second = (np.arange(n) - starts[rows]) >= change[rows]
+        k[:, :4] = pref[rows]
+        k[:, 4:] = tails[rows, second.astype(np.int64)]
+        # buckets in shuffled order, each keeping its own order
+        order = rng.permutation(nb)
+        k = np.concatenate([k[starts[b]: starts[b] + sizes[b]] for b in order])
     return k
 
 
-@pytest.mark.parametrize("case", ["uniform", "one_prefix", "mixed_buckets", "lengths_up_to_4", "near_64"])
+@pytest.mark.parametrize("case", ["uniform", "one_prefix", "mixed_buckets", "lengths_up_to_4", "near_64",
+                                  "change_points"])
 @pytest.mark.parametrize("descending", [False, True])
 def test_bucketed_strings_pairs(case, descending):
-    keys = _strings(case)
+    keys = _strings(case, 384 * 8192) if case == "change_points" else _strings(case)
     n = keys.shape[0]
     vals = np.arange(n, dtype=np.uint32)
     _say(f"bucketed strings {case} desc={descending} n={n}")
