@@ -32,7 +32,7 @@
  *     RS_FLAG_VALIDATE, and rs_sort_keys / rs_sort_pairs of base-27 strings
  *     of 16 symbols from 2^21 keys (the prescanned passes), which sort the
  *     buckets of the four leading symbols one by one and read back how many
- *     long buckets of distinct keys need the batched passes.  While the
+ *     long buckets whose keys differ need the batched passes.  While the
  *     stream is being captured those strings run all eight passes instead,
  *     with no wait.
  *   - Order is ascending and stable: equal keys keep their input order

@@ -105,7 +105,7 @@ struct Plan {
   SegLayout seg;                       // batched form
   // base-27 16-symbol strings, prescanned: the passes over the four leading
   // symbols, then every bucket of equal leading symbols sorted on its own
-  // (rs_str_buckets.h); long buckets of distinct keys go through the
+  // (rs_str_buckets.h); long buckets whose keys differ go through the
   // batched passes over the other twelve symbols (layout bseg, sized for
   // blist_cap buckets, at off_bseg; it reuses the alternate arrays)
   bool str_buckets = false;

@@ -181,13 +181,6 @@ static rs_status run_passes(const Plan &pl, const Digit *digits, const void *key
   return RS_OK;
 }
 
-// Base-27 strings of 16 symbols by buckets (rs_str_buckets.h): the two
-// passes over the four leading symbols order the array by its 27^4 leading
-// cells; each cell's bucket is then sorted by the twelve other symbols, in
-// place in the output.  Long buckets of distinct keys, if any, are listed on
-// the device; the list's length is read back (the one synchronisation of
-// this form) and they go through the batched passes over the twelve
-// symbols.
 // Workgroups of 256 threads of a kernel that run at once on the whole chip.
 template <auto KERNEL>
 static uint32_t resident_grid() {
@@ -204,6 +197,13 @@ static uint32_t resident_grid() {
   return grid;
 }
 
+// Base-27 strings of 16 symbols by buckets (rs_str_buckets.h): the two
+// passes over the four leading symbols order the array by its 27^4 leading
+// cells; each cell's bucket is then sorted by the twelve other symbols, in
+// place in the output.  Buckets of more than 64 keys that are not all equal
+// in those symbols, if any, are listed on the device; the list's length is
+// read back (the one synchronisation of this form) and they go through the
+// batched passes over the twelve symbols.
 static rs_status run_str_buckets(const Plan &pl, const void *keys_in, void *keys_out, const uint32_t *vals_in,
                                  uint32_t *vals_out, void *tmp, hipStream_t stream) {
   char *base = (char *)tmp;
@@ -276,7 +276,7 @@ static rs_status run_str_buckets(const Plan &pl, const void *keys_in, void *keys
     return fail(RS_ERR_HIP, "reading the count of long buckets");
   if (nlong == 0) return RS_OK;
   if (nlong > pl.blist_cap) return fail(RS_ERR_HIP, "long-bucket list overflow");
-  // the long buckets of distinct keys: the batched passes over the twelve
+  // the listed long buckets: the batched passes over the twelve
   // symbols, in place, with the alternate arrays as their scratch
   SegLayout L;
   std::string why;

@@ -1,9 +1,9 @@
 """Base-27 strings of 16 symbols from 2^21 keys (the prescanned passes): the passes over the four
 leading symbols, then every bucket of equal leading symbols sorted on its own
-by the other twelve (waves for buckets of at most 64 keys, already ordered
-buckets of equal keys left as they are, the batched passes for long buckets
-of distinct keys).  Every case is compared with the oracle element by
-element, ascending and descending, with and without values."""
+by the other twelve (waves for buckets of at most 64 keys, buckets of equal
+keys left as they are, the batched passes for longer buckets whose keys
+differ).  Every case is compared with the oracle element by element,
+ascending and descending, with and without values."""
 from __future__ import annotations
 
 import sys
