@@ -225,11 +225,8 @@ static rs_status run_str_buckets(const Plan &pl, const void *keys_in, void *keys
   // S of the four leading symbols, and each bucket's start
   StrBucketParams q;
   memset(&q, 0, sizeof q);
-  q.lead.pos = 0;
-  q.lead.width = 4;
-  q.lead.base = 27;
-  q.lead.cx = pl.key.descending ? ~0u : 0u;
-  q.lead.ca = pl.key.descending ? kStrBucketCells : 0u;
+  q.lead_cx = pl.key.descending ? ~0u : 0u;
+  q.lead_ca = pl.key.descending ? kStrBucketCells : 0u;
   q.n = pl.n;
   q.counts = (uint32_t *)(base + pl.off_bcounts);
   q.mixed = (uint8_t *)(base + pl.off_bmixed);

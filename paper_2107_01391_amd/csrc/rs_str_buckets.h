@@ -62,8 +62,24 @@ __device__ __forceinline__ void str27_rest_words(const Str16 &k, uint32_t r[3]) 
   for (int w = 1; w < 4; ++w) r[w - 1] = k.w[w] & 0x1f1f1f1fu;
 }
 
+// The cell of the four leading symbols (bytes 0..3, the first most
+// significant), each symbol as the passes' codec (DigitStr16) takes it, so
+// that for any bytes it is the cell the two passes over those symbols order
+// the array by; unrolled, with no per-symbol branch.  (cell ^ cx) + ca
+// complements it for descending order.
+__device__ __forceinline__ uint32_t str27_lead_cell(const Str16 &k, uint32_t cx, uint32_t ca) {
+  const uint32_t m = k.w[0];
+  uint32_t cell = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint32_t byte = m >> (8 * j) & 0xffu, d = byte - 96u;
+    cell = cell * 27u + (byte == 0u ? 0u : (d < 26u ? d : 26u));
+  }
+  return (cell ^ cx) + ca;
+}
+
 struct StrBucketParams {
-  DigitStr16 lead;        // cell of the four leading symbols, as the passes order them
+  uint32_t lead_cx, lead_ca;  // descending complement of the leading cell
   uint64_t n;
   uint32_t *counts;       // [kStrBucketCells], zero before the count kernel
   uint8_t *mixed;         // [kStrBucketCells], zero before the count kernel
@@ -96,7 +112,7 @@ __global__ __launch_bounds__(BLOCK) void rs_str_bucket_count(const StrBucketPara
   bool omix = false;
   if (a > 0) {  // the key before the range: a run of its cell continues here
     const Str16 p = keys[a - 1];
-    oc = q.lead(p);
+    oc = str27_lead_cell(p, q.lead_cx, q.lead_ca);
     str27_rest_words(p, orr);
   }
   for (uint64_t s0 = a; s0 < b; s0 += (uint64_t)U * kWave) {
@@ -111,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void rs_str_bucket_count(const StrBucketPara
       const uint64_t e0 = s0 + (uint64_t)u * kWave;
       if (e0 >= b) break;  // uniform
       const bool valid = e0 + lane < b;  // a prefix of the wave
-      const uint32_t c = valid ? q.lead(kk[u]) : kNone;
+      const uint32_t c = valid ? str27_lead_cell(kk[u], q.lead_cx, q.lead_ca) : kNone;
       uint32_t r[3], pr[3];
       str27_rest_words(kk[u], r);
       uint32_t pc = __shfl_up(c, 1, kWave);
